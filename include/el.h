@@ -1,0 +1,173 @@
+/*
+ * el.h -- C ABI of the elastic PACT operator pair on one AMD Instinct MI355X (gfx950).
+ *
+ * The library applies the discrete forward operator H and its exact adjoint
+ * H^T of Mitsuhashi et al., "A forward-adjoint operator pair based on the
+ * elastic wave equation for use in transcranial photoacoustic computed
+ * tomography":
+ *
+ *   p_hat = H p0      H   = M' T'_{M-1} ... T'_1 T'_0      (Appendix, eq. HPML)
+ *   p_adj = H^T y     H^T = T'_0^T ... T'_{M-1}^T M'^T     (Appendix, eq. adjHPML)
+ *
+ * where each T'_m advances the 4th-order staggered-grid velocity-stress FDTD
+ * scheme of the lossy heterogeneous elastic wave equation (Sec. 2.2, eq. it;
+ * Appendix, C-PML memory-variable updates) by one step dt, T'_0 injects the
+ * initial pressure as the isotropic stress -p0/3 (Sec. 2.1, eq. Ini; Sec. 3,
+ * eq. initialp0) and M' samples the pressure -(s11+s22+s33) at the
+ * transducers by trilinear interpolation (Sec. 3, eq. interpgrid).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Grid: nx*ny*nz cells, x fastest: cell (i,j,k) is element i + nx*(j + ny*k)
+ *    of every volume array.  Normal stresses, lambda, mu, p0 sit on cell
+ *    (i,j,k); u1, u2, u3 at (i+1/2,j,k), (i,j+1/2,k), (i,j,k+1/2); s12, s13,
+ *    s23 at (i+1/2,j+1/2,k), (i+1/2,j,k+1/2), (i,j+1/2,k+1/2).  Fields are
+ *    zero outside the grid.
+ *  - The C-PML occupies the outer npml cells of each face (inside the grid).
+ *  - Time: nsteps = M samples t_m = m dt, m = 0..M-1, i.e. M-1 updates.
+ *  - Traces are double precision, time-major: traces[m*L + l].
+ *  - Units are SI: Pa, kg/m^3, 1/s (velocity damping rate of the diffusive
+ *    absorption model, Sec. 2.1 eq. subeq1), metres, seconds.
+ *  - Memory: every pointer marked (device) is device memory of the GPU that
+ *    is current when the call is made; (host) is ordinary host memory.  The
+ *    caller owns every buffer, the workspace included; the library never
+ *    allocates device memory.
+ *  - Streams: `stream` is a hipStream_t passed as void* (NULL = the default
+ *    stream).  Operations are asynchronous with respect to the host unless
+ *    stated otherwise; successive operations on one plan are ordered even
+ *    when issued on different streams.
+ *  - Errors: every call returns EL_OK (0) or a negative el_status; the detail
+ *    of the last failure on the calling thread is returned by el_last_error().
+ *    Argument checks run on the host before anything is enqueued, so a
+ *    rejected call leaves device memory untouched.  No C++ exception crosses
+ *    this interface.
+ */
+#ifndef EL_H
+#define EL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t el_status;
+#define EL_OK         0
+#define EL_EINVAL    -1   /* malformed argument, bad material value, null pointer          */
+#define EL_EUNSTABLE -2   /* CFL above 6/(7 sqrt 3) or dt*alpha outside [0,1)               */
+#define EL_ERANGE    -3   /* a receiver outside [0, n-1]*dx on some axis                    */
+#define EL_ENOMEM    -4   /* workspace smaller than el_plan_bytes() says                    */
+#define EL_EDEVICE   -5   /* a HIP runtime call failed                                      */
+
+#define EL_F32 0          /* fields, stencils, p0 and p_adj in float  */
+#define EL_F64 1          /* fields, stencils, p0 and p_adj in double */
+
+typedef struct {
+    int32_t nx, ny, nz;   /* cells per axis, C-PML included; each >= 4 and >= 2*npml + 2      */
+    double  dx;           /* grid spacing (m), the same on every axis                          */
+    double  dt;           /* time step (s)                                                     */
+    int32_t nsteps;       /* M >= 1 trace samples (M-1 updates)                                */
+    int32_t npml;         /* C-PML thickness in cells on every face; 0 = no layer              */
+    double  pml_R;        /* target reflection of the layer; <= 0 selects 1e-3                 */
+    double  pml_npower;   /* damping profile power; <= 0 selects 2                             */
+    double  pml_f0;       /* frequency (Hz) of the profile's beta = pi f0 (1 - xi);            */
+                          /*   <= 0 selects 1500 / (8 dx)                                      */
+    int32_t precision;    /* EL_F32 or EL_F64                                                  */
+} el_grid;
+
+typedef struct el_plan_* el_plan;
+
+/* Library version string (static storage). */
+const char *el_version(void);
+
+/* Name of a status code (static storage). */
+const char *el_status_string(el_status status);
+
+/* Detail of the last failed call on the calling thread ("" if none). */
+const char *el_last_error(void);
+
+/*
+ * Host-only checks of a grid and a receiver set: sizes, spacing, PML
+ * thickness, precision, and that every receiver lies in [0, n-1]*dx (up to
+ * 1e-9 cells of rounding; such receivers are clamped onto the box).
+ * rec_xyz (host): nrec x 3 doubles, metres from the centre of cell (0,0,0),
+ * columns x, y, z.  nrec may be 0 (rec_xyz may then be NULL).
+ * Returns EL_EINVAL or EL_ERANGE on failure.  Touches no device.
+ */
+el_status el_grid_check(const el_grid *grid, const double *rec_xyz, int32_t nrec);
+
+/*
+ * Device workspace bytes a plan of this grid and receiver count needs
+ * (fields, material maps, C-PML boundary slabs, PML tables, receiver
+ * tables, reduction scratch).  Host-only; *bytes is written on success.
+ */
+el_status el_plan_bytes(const el_grid *grid, int32_t nrec, size_t *bytes);
+
+/*
+ * Build a plan: validate, copy the material maps into the workspace,
+ * compute the C-PML profiles (Appendix A.1-A.2, kappa = 1) and the
+ * trilinear receiver tables (Sec. 3, eq. interpgrid).
+ *   lambda, mu, rho, alpha (device): N = nx*ny*nz floats each, cell values
+ *       in Pa, Pa, kg/m^3, 1/s.  Checked on the device: rho > 0, mu >= 0,
+ *       lambda + 2 mu > 0, 0 <= dt*alpha < 1, all finite (EL_EINVAL /
+ *       EL_EUNSTABLE), and max sqrt((lambda+2mu)/rho) dt/dx <= 6/(7 sqrt 3)
+ *       (EL_EUNSTABLE).  They may be freed once this call returns.
+ *   rec_xyz (host): nrec x 3 doubles as in el_grid_check().
+ *   workspace (device): at least el_plan_bytes() bytes, 256-byte aligned,
+ *       owned by the caller, valid until el_plan_destroy().
+ * Synchronous: returns after the stream has drained the setup work.
+ * On success *out receives the plan; on failure *out is NULL.
+ */
+el_status el_plan_create(el_plan *out, const el_grid *grid,
+                         const float *lambda, const float *mu, const float *rho, const float *alpha,
+                         const double *rec_xyz, int32_t nrec,
+                         void *workspace, size_t workspace_bytes, void *stream);
+
+/* Release the plan's host state.  The workspace stays the caller's. */
+el_status el_plan_destroy(el_plan plan);
+
+/*
+ * traces = H p0  (Appendix, eq. STforHPML).
+ *   p0 (device): N elements, float for EL_F32 plans, double for EL_F64 plans.
+ *   traces (device): nsteps x nrec doubles, time-major, fully overwritten.
+ * Asynchronous on `stream`.
+ */
+el_status el_forward(el_plan plan, const void *p0, double *traces, void *stream);
+
+/*
+ * p_adj = H^T y, by the backward recursion v_{m-1} = Theta^T y_{m-1} + W'^T v_m
+ * with v_{M-1} = Theta^T y_{M-1} and p_adj = tau'^T v_0 (Sec. 4, eq. Adjup;
+ * Appendix eq. AdjupPML read with index m-1).
+ *   y (device): nsteps x nrec doubles, time-major.
+ *   p_adj (device): N elements of the plan's precision, fully overwritten.
+ * Asynchronous on `stream`.
+ */
+el_status el_adjoint(el_plan plan, const double *y, void *p_adj, void *stream);
+
+/*
+ * *out = <a, b> accumulated in double (the inner products of the paper's
+ * dot-product test, Sec. 5).  space 0: a, b (device) hold N elements of the
+ * plan's precision; space 1: a, b (device) hold nsteps*nrec doubles.
+ * out (device): one double.  Deterministic (fixed reduction order).
+ * Asynchronous on `stream`.
+ */
+el_status el_dot_f64(el_plan plan, int32_t space, const void *a, const void *b, double *out, void *stream);
+
+/*
+ * Device pointer and element count of one of the plan's wavefield arrays,
+ * for inspection after an operation has completed: id 0..2 = u1, u2, u3;
+ * 3..8 = s11, s22, s33, s23, s13, s12 (elements of the plan's precision).
+ * After el_forward they hold u_{M-3/2} and sigma_{M-1}; after el_adjoint
+ * they hold the adjoint state of step 0.
+ */
+el_status el_plan_field(el_plan plan, int32_t id, void **ptr, size_t *count);
+
+/* Number of cells N and of receivers L of a plan. */
+el_status el_plan_sizes(el_plan plan, int64_t *ncells, int32_t *nrec, int32_t *nsteps);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* EL_H */

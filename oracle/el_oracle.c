@@ -42,7 +42,8 @@
  *  - injection tau' = -1/3 on sigma11, sigma22, sigma33 (Sec. 3, eq. Ini and
  *    eq. initialp0; the Appendix's -I conflicts with eq. p0);
  *  - measurement row  -R_l (sigma11+sigma22+sigma33), trilinear R_l on the
- *    normal-stress grid, base index clamped to n-2;
+ *    normal-stress grid, base index clamped to n-2; a receiver must lie in
+ *    [0, n-1] cells on each axis (1e-9 cells of rounding allowed, clamped);
  *  - nsteps = M samples including m = 0, hence M-1 applications of W';
  *  - adjoint recursion v_{m-1} = Theta^T p_{m-1} + W^T v_m (Sec. 4, eq. Adjup);
  *  - memory variable phi^{ij} lives at the u^i point, psi^{ij} at the
@@ -498,7 +499,10 @@ eo_model *eo_model_create(const eo_grid *g, const float *lam, const float *mu, c
         double f[3];
         for (int a = 0; a < 3; ++a) {
             double x = rec[3 * l + a] / g->dx;
-            if (!(x >= 0.0 && x <= (double)(m->n[a] - 1))) { eo_model_free(m); return NULL; }
+            /* inside [0, n-1] up to 1e-9 cells of rounding, then clamped onto the box */
+            if (!(x >= -1e-9 && x <= (double)(m->n[a] - 1) + 1e-9)) { eo_model_free(m); return NULL; }
+            if (x < 0.0) x = 0.0;
+            if (x > (double)(m->n[a] - 1)) x = (double)(m->n[a] - 1);
             int bb = (int)floor(x);
             if (bb > m->n[a] - 2) bb = m->n[a] - 2;
             b[a] = bb;

@@ -1,0 +1,490 @@
+// Host side of the C ABI declared in include/el.h: validation, workspace
+// layout, C-PML profiles, receiver tables and the time loops of H and H^T.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "el_impl.h"
+
+using namespace el;
+
+namespace {
+
+thread_local std::string g_err;
+
+el_status fail(el_status st, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+el_status fail(el_status st, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+el_status hip_fail(hipError_t e, const char *what) {
+    return fail(EL_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr, what)                        \
+    do {                                           \
+        hipError_t e_ = (expr);                    \
+        if (e_ != hipSuccess) return hip_fail(e_, what); \
+    } while (0)
+
+size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+// 4th-order staggered 3-D stability bound: c dt/dx <= 1 / (sqrt(3) (9/8 + 1/24)).
+const double kCflMax = 6.0 / (7.0 * std::sqrt(3.0));
+
+// Receivers may sit up to this many cells outside [0, n-1] (rounding of x/dx); they are clamped onto the box.
+const double kRecSlack = 1e-9;
+
+}  // namespace
+
+struct el_plan_ {
+    el_grid g;
+    int nrec;
+    long long N;
+    Layout L;
+    char *ws;
+    int device;
+    Dev<float> df;
+    Dev<double> dd;
+    Rec rec;
+    hipEvent_t done;
+    double cmax;
+};
+
+namespace el {
+
+bool layout(const el_grid &g, int nrec, Layout *L) {
+    const size_t es = g.precision == EL_F64 ? 8 : 4;
+    const size_t N = (size_t)g.nx * g.ny * g.nz;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off += align256(bytes);
+        return o;
+    };
+    for (int f = 0; f < NFIELD; ++f) L->field[f] = take(N * es);
+    for (int m = 0; m < 4; ++m) L->map[m] = take(N * es);
+    const int P = g.npml;
+    const size_t W = P > 0 ? 2 * (size_t)(P + 1) : 0;
+    const size_t ns[3] = {W * g.ny * g.nz, (size_t)g.nx * W * g.nz, (size_t)g.nx * g.ny * W};
+    const int n[3] = {g.nx, g.ny, g.nz};
+    for (int a = 0; a < 3; ++a)
+        for (int q = 0; q < 6; ++q) L->mem[a][q] = P > 0 ? take(ns[a] * es) : 0;
+    for (int a = 0; a < 3; ++a)
+        for (int h = 0; h < 2; ++h) {
+            L->pa[a][h] = P > 0 ? take(n[a] * es) : 0;
+            L->pb[a][h] = P > 0 ? take(n[a] * es) : 0;
+        }
+    const size_t E = 8 * (size_t)std::max(nrec, 1);
+    L->rec_idx = take(E * 8);
+    L->rec_w = take(E * 8);
+    L->csr_pt = take(E * 8);
+    L->csr_row = take((E + 1) * 4);
+    L->csr_rec = take(E * 4);
+    L->csr_w = take(E * 8);
+    L->stats = take(16 * 8);
+    L->partial = take(7 * kDotBlocks * 8);
+    L->total = off;
+    return true;
+}
+
+}  // namespace el
+
+extern "C" {
+
+const char *el_version(void) { return "elastic-pact-mi355x 0.1.0 (gfx950)"; }
+
+const char *el_status_string(el_status s) {
+    switch (s) {
+        case EL_OK: return "EL_OK";
+        case EL_EINVAL: return "EL_EINVAL";
+        case EL_EUNSTABLE: return "EL_EUNSTABLE";
+        case EL_ERANGE: return "EL_ERANGE";
+        case EL_ENOMEM: return "EL_ENOMEM";
+        case EL_EDEVICE: return "EL_EDEVICE";
+        default: return "EL_UNKNOWN";
+    }
+}
+
+const char *el_last_error(void) { return g_err.c_str(); }
+
+el_status el_grid_check(const el_grid *g, const double *rec, int32_t nrec) {
+    if (!g) return fail(EL_EINVAL, "grid is NULL");
+    if (g->nx < 4 || g->ny < 4 || g->nz < 4)
+        return fail(EL_EINVAL, "grid %dx%dx%d: every axis needs at least 4 cells", g->nx, g->ny, g->nz);
+    if ((long long)g->nx * g->ny * g->nz > (1LL << 40)) return fail(EL_EINVAL, "grid too large");
+    if (!(g->dx > 0) || !std::isfinite(g->dx)) return fail(EL_EINVAL, "dx must be positive and finite");
+    if (!(g->dt > 0) || !std::isfinite(g->dt)) return fail(EL_EINVAL, "dt must be positive and finite");
+    if (g->nsteps < 1) return fail(EL_EINVAL, "nsteps must be >= 1");
+    if (g->npml < 0) return fail(EL_EINVAL, "npml must be >= 0");
+    const int n[3] = {g->nx, g->ny, g->nz};
+    for (int a = 0; a < 3; ++a)
+        if (g->npml > 0 && n[a] < 2 * g->npml + 2)
+            return fail(EL_EINVAL, "axis %d has %d cells, fewer than 2*npml+2 = %d", a, n[a], 2 * g->npml + 2);
+    if (g->precision != EL_F32 && g->precision != EL_F64) return fail(EL_EINVAL, "precision must be EL_F32 or EL_F64");
+    if (nrec < 0) return fail(EL_EINVAL, "nrec must be >= 0");
+    if (nrec > (1 << 26)) return fail(EL_EINVAL, "too many receivers");
+    if (nrec > 0 && !rec) return fail(EL_EINVAL, "rec_xyz is NULL");
+    for (int l = 0; l < nrec; ++l)
+        for (int a = 0; a < 3; ++a) {
+            const double x = rec[3 * l + a] / g->dx;
+            if (!(x >= -kRecSlack && x <= (double)(n[a] - 1) + kRecSlack))
+                return fail(EL_ERANGE, "receiver %d axis %d at %.6g cells is outside [0, %d]", l, a, x, n[a] - 1);
+        }
+    return EL_OK;
+}
+
+el_status el_plan_bytes(const el_grid *g, int32_t nrec, size_t *bytes) {
+    el_status st = el_grid_check(g, nullptr, 0);
+    if (st != EL_OK) return st;
+    if (nrec < 0) return fail(EL_EINVAL, "nrec must be >= 0");
+    if (!bytes) return fail(EL_EINVAL, "bytes is NULL");
+    Layout L;
+    layout(*g, nrec, &L);
+    *bytes = L.total;
+    return EL_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// C-PML profile of one axis (Appendix A.1-A.2, kappa = 1): with xi the depth into
+// the layer over its thickness, measured from planes P and n-1-P and clamped to
+// [0, 1], d = d0 xi^npow, beta = pi f0 (1 - xi), b = exp(-(d + beta) dt),
+// a = d / (d + beta) (b - 1); a = 0 where xi = 0.
+void pml_axis(const el_grid &g, int n, double d0, double f0, double npow, int half, std::vector<double> &a,
+              std::vector<double> &b) {
+    a.assign(n, 0.0);
+    b.assign(n, 1.0);
+    const int P = g.npml;
+    for (int i = 0; i < n; ++i) {
+        const double x = i + 0.5 * half;
+        double depth = 0.0;
+        if (x < P) depth = P - x;
+        if (x > n - 1 - P) depth = x - (n - 1 - P);
+        double xi = depth / P;
+        if (xi > 1.0) xi = 1.0;
+        if (xi > 0.0) {
+            const double d = d0 * std::pow(xi, npow);
+            const double beta = M_PI * f0 * (1.0 - xi);
+            b[i] = std::exp(-(d + beta) * g.dt);
+            a[i] = d / (d + beta) * (b[i] - 1.0);
+        } else {
+            b[i] = std::exp(-(M_PI * f0) * g.dt);
+        }
+    }
+}
+
+template <typename T>
+void bind(Dev<T> &d, el_plan_ *p) {
+    const el_grid &g = p->g;
+    char *ws = p->ws;
+    d.nx = g.nx;
+    d.ny = g.ny;
+    d.nz = g.nz;
+    d.nxy = (long long)g.nx * g.ny;
+    d.dt = T(g.dt);
+    d.inv_dx = T(1.0 / g.dx);
+    for (int f = 0; f < NFIELD; ++f) d.f[f] = reinterpret_cast<T *>(ws + p->L.field[f]);
+    d.lam = reinterpret_cast<T *>(ws + p->L.map[0]);
+    d.mu = reinterpret_cast<T *>(ws + p->L.map[1]);
+    d.rho = reinterpret_cast<T *>(ws + p->L.map[2]);
+    d.alpha = reinterpret_cast<T *>(ws + p->L.map[3]);
+    d.P = g.npml;
+    const int n[3] = {g.nx, g.ny, g.nz};
+    for (int a = 0; a < 3; ++a) d.hi[a] = n[a] - 1 - g.npml;
+    d.W = g.npml > 0 ? 2 * (g.npml + 1) : 0;
+    for (int a = 0; a < 3; ++a) {
+        for (int h = 0; h < 2; ++h) {
+            d.pa[a][h] = g.npml > 0 ? reinterpret_cast<T *>(ws + p->L.pa[a][h]) : nullptr;
+            d.pb[a][h] = g.npml > 0 ? reinterpret_cast<T *>(ws + p->L.pb[a][h]) : nullptr;
+        }
+        for (int q = 0; q < 6; ++q) d.mem[a][q] = g.npml > 0 ? reinterpret_cast<T *>(ws + p->L.mem[a][q]) : nullptr;
+    }
+}
+
+template <typename T>
+el_status upload_pml(el_plan_ *p, Dev<T> &d, hipStream_t s) {
+    const el_grid &g = p->g;
+    if (g.npml <= 0) return EL_OK;
+    const double R = g.pml_R > 0 ? g.pml_R : 1e-3;
+    const double npow = g.pml_npower > 0 ? g.pml_npower : 2.0;
+    const double f0 = g.pml_f0 > 0 ? g.pml_f0 : 1500.0 / (8.0 * g.dx);
+    const double d0 = -(npow + 1.0) * p->cmax * std::log(R) / (2.0 * g.npml * g.dx);
+    const int n[3] = {g.nx, g.ny, g.nz};
+    std::vector<double> a, b;
+    for (int ax = 0; ax < 3; ++ax)
+        for (int h = 0; h < 2; ++h) {
+            pml_axis(g, n[ax], d0, f0, npow, h, a, b);
+            std::vector<T> at(a.begin(), a.end()), bt(b.begin(), b.end());
+            HIP_TRY(hipMemcpyAsync(const_cast<T *>(d.pa[ax][h]), at.data(), n[ax] * sizeof(T), hipMemcpyHostToDevice, s),
+                    "copy PML a");
+            HIP_TRY(hipMemcpyAsync(const_cast<T *>(d.pb[ax][h]), bt.data(), n[ax] * sizeof(T), hipMemcpyHostToDevice, s),
+                    "copy PML b");
+            HIP_TRY(hipStreamSynchronize(s), "PML upload");
+        }
+    return EL_OK;
+}
+
+// Trilinear weights on the normal-stress grid (Sec. 3, eq. interpgrid): base index
+// floor(x/dx) clamped to n-2, fraction x/dx - base; corner c = (c&1, c>>1&1, c>>2&1).
+el_status upload_receivers(el_plan_ *p, const double *rec, hipStream_t s) {
+    const el_grid &g = p->g;
+    const int L = p->nrec;
+    const int n[3] = {g.nx, g.ny, g.nz};
+    std::vector<long long> idx(8 * (size_t)L);
+    std::vector<double> w(8 * (size_t)L);
+    for (int l = 0; l < L; ++l) {
+        int b[3];
+        double f[3];
+        for (int a = 0; a < 3; ++a) {
+            const double x = std::min(std::max(rec[3 * l + a] / g.dx, 0.0), (double)(n[a] - 1));
+            int bb = (int)std::floor(x);
+            if (bb > n[a] - 2) bb = n[a] - 2;
+            b[a] = bb;
+            f[a] = x - bb;
+        }
+        for (int c = 0; c < 8; ++c) {
+            const int ox = c & 1, oy = (c >> 1) & 1, oz = (c >> 2) & 1;
+            idx[8 * l + c] = (b[0] + ox) + (long long)g.nx * ((b[1] + oy) + (long long)g.ny * (b[2] + oz));
+            w[8 * l + c] = (ox ? f[0] : 1 - f[0]) * (oy ? f[1] : 1 - f[1]) * (oz ? f[2] : 1 - f[2]);
+        }
+    }
+    // grid-point-major transpose: entries sorted by (cell, receiver, corner)
+    std::vector<int> order(8 * (size_t)L);
+    for (size_t e = 0; e < order.size(); ++e) order[e] = (int)e;
+    std::sort(order.begin(), order.end(), [&](int x, int y) { return idx[x] != idx[y] ? idx[x] < idx[y] : x < y; });
+    std::vector<long long> pt;
+    std::vector<int> row, erec;
+    std::vector<double> ew;
+    for (size_t e = 0; e < order.size(); ++e) {
+        const int o = order[e];
+        if (pt.empty() || pt.back() != idx[o]) {
+            pt.push_back(idx[o]);
+            row.push_back((int)e);
+        }
+        erec.push_back(o / 8);
+        ew.push_back(w[o]);
+    }
+    row.push_back((int)order.size());
+    char *ws = p->ws;
+    Rec &r = p->rec;
+    r.nrec = L;
+    r.idx = reinterpret_cast<long long *>(ws + p->L.rec_idx);
+    r.w = reinterpret_cast<double *>(ws + p->L.rec_w);
+    r.npts = (int)pt.size();
+    r.pt = reinterpret_cast<long long *>(ws + p->L.csr_pt);
+    r.row = reinterpret_cast<int *>(ws + p->L.csr_row);
+    r.ent_rec = reinterpret_cast<int *>(ws + p->L.csr_rec);
+    r.ent_w = reinterpret_cast<double *>(ws + p->L.csr_w);
+    if (L > 0) {
+        HIP_TRY(hipMemcpyAsync((void *)r.idx, idx.data(), idx.size() * 8, hipMemcpyHostToDevice, s), "copy receivers");
+        HIP_TRY(hipMemcpyAsync((void *)r.w, w.data(), w.size() * 8, hipMemcpyHostToDevice, s), "copy receivers");
+        HIP_TRY(hipMemcpyAsync((void *)r.pt, pt.data(), pt.size() * 8, hipMemcpyHostToDevice, s), "copy receivers");
+        HIP_TRY(hipMemcpyAsync((void *)r.row, row.data(), row.size() * 4, hipMemcpyHostToDevice, s), "copy receivers");
+        HIP_TRY(hipMemcpyAsync((void *)r.ent_rec, erec.data(), erec.size() * 4, hipMemcpyHostToDevice, s),
+                "copy receivers");
+        HIP_TRY(hipMemcpyAsync((void *)r.ent_w, ew.data(), ew.size() * 8, hipMemcpyHostToDevice, s), "copy receivers");
+        HIP_TRY(hipStreamSynchronize(s), "receiver upload");
+    }
+    return EL_OK;
+}
+
+el_status check_plan(el_plan p) {
+    if (!p) return fail(EL_EINVAL, "plan is NULL");
+    int dev = -1;
+    HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
+    if (dev != p->device) return fail(EL_EINVAL, "current device %d is not the plan's device %d", dev, p->device);
+    return EL_OK;
+}
+
+template <typename T>
+el_status run_forward(el_plan p, Dev<T> &d, const T *p0, double *traces, hipStream_t s) {
+    const int M = p->g.nsteps, L = p->nrec;
+    HIP_TRY(launch_zero_state(d, s), "zero state");
+    HIP_TRY(launch_inject(d, p0, s), "inject");
+    HIP_TRY(launch_gather(d, p->rec, traces, s), "gather");
+    for (int m = 1; m < M; ++m) {
+        HIP_TRY(launch_velocity(d, s), "velocity pass");
+        HIP_TRY(launch_stress(d, s), "stress pass");
+        HIP_TRY(launch_gather(d, p->rec, traces + (size_t)m * L, s), "gather");
+    }
+    return EL_OK;
+}
+
+template <typename T>
+el_status run_adjoint(el_plan p, Dev<T> &d, const double *y, T *out, hipStream_t s) {
+    const int M = p->g.nsteps, L = p->nrec;
+    HIP_TRY(launch_zero_state(d, s), "zero state");
+    HIP_TRY(launch_scatter(d, p->rec, y + (size_t)(M - 1) * L, s), "scatter");
+    for (int m = M - 1; m >= 1; --m) {
+        HIP_TRY(launch_adj_velocity(d, s), "adjoint velocity pass");
+        HIP_TRY(launch_adj_stress(d, s), "adjoint stress pass");
+        HIP_TRY(launch_scatter(d, p->rec, y + (size_t)(m - 1) * L, s), "scatter");
+    }
+    HIP_TRY(launch_extract(d, out, s), "extract");
+    return EL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+el_status el_plan_create(el_plan *out, const el_grid *grid, const float *lam, const float *mu, const float *rho,
+                         const float *alpha, const double *rec, int32_t nrec, void *workspace,
+                         size_t workspace_bytes, void *stream) {
+    if (!out) return fail(EL_EINVAL, "out is NULL");
+    *out = nullptr;
+    el_status st = el_grid_check(grid, rec, nrec);
+    if (st != EL_OK) return st;
+    if (!lam || !mu || !rho || !alpha) return fail(EL_EINVAL, "a material map is NULL");
+    if (!workspace) return fail(EL_EINVAL, "workspace is NULL");
+    if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0) return fail(EL_EINVAL, "workspace is not 256-byte aligned");
+    Layout L;
+    layout(*grid, nrec, &L);
+    if (workspace_bytes < L.total)
+        return fail(EL_ENOMEM, "workspace has %zu bytes, the plan needs %zu", workspace_bytes, L.total);
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
+
+    el_plan_ *p = new el_plan_();
+    p->g = *grid;
+    p->nrec = nrec;
+    p->N = (long long)grid->nx * grid->ny * grid->nz;
+    p->L = L;
+    p->ws = static_cast<char *>(workspace);
+    p->device = dev;
+    auto bail = [&](el_status e) {
+        if (p->done) (void)hipEventDestroy(p->done);
+        delete p;
+        return e;
+    };
+
+    // media checks on the device, in double
+    double *stats = reinterpret_cast<double *>(p->ws + L.stats);
+    double *partial = reinterpret_cast<double *>(p->ws + L.partial);
+    hipError_t e = launch_media_stats(lam, mu, rho, alpha, p->N, grid->dt, stats, partial, s);
+    if (e != hipSuccess) return bail(hip_fail(e, "media statistics"));
+    double hs[7];
+    e = hipMemcpyAsync(hs, stats, sizeof hs, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return bail(hip_fail(e, "media statistics"));
+    if (hs[6] > 0) return bail(fail(EL_EINVAL, "%.0f non-finite material values", hs[6]));
+    if (!(hs[1] > 0)) return bail(fail(EL_EINVAL, "rho must be > 0 (min %.6g)", hs[1]));
+    if (hs[2] < 0) return bail(fail(EL_EINVAL, "mu must be >= 0 (min %.6g)", hs[2]));
+    if (!(hs[3] > 0)) return bail(fail(EL_EINVAL, "lambda + 2 mu must be > 0 (min %.6g)", hs[3]));
+    if (hs[5] < 0 || hs[4] >= 1.0)
+        return bail(fail(EL_EUNSTABLE, "dt*alpha must lie in [0, 1) (range %.6g .. %.6g)", hs[5], hs[4]));
+    p->cmax = std::sqrt(hs[0]);
+    const double cfl = p->cmax * grid->dt / grid->dx;
+    if (cfl > kCflMax)
+        return bail(fail(EL_EUNSTABLE, "CFL c_max dt/dx = %.6g exceeds the 4th-order staggered limit %.6g", cfl, kCflMax));
+
+    e = hipEventCreateWithFlags(&p->done, hipEventDisableTiming);
+    if (e != hipSuccess) return bail(hip_fail(e, "event"));
+    if (grid->precision == EL_F64) {
+        bind(p->dd, p);
+        e = launch_convert_maps(p->dd, lam, mu, rho, alpha, s);
+        if (e != hipSuccess) return bail(hip_fail(e, "copy maps"));
+        st = upload_pml(p, p->dd, s);
+    } else {
+        bind(p->df, p);
+        e = launch_convert_maps(p->df, lam, mu, rho, alpha, s);
+        if (e != hipSuccess) return bail(hip_fail(e, "copy maps"));
+        st = upload_pml(p, p->df, s);
+    }
+    if (st != EL_OK) return bail(st);
+    st = upload_receivers(p, rec, s);
+    if (st != EL_OK) return bail(st);
+    e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return bail(hip_fail(e, "plan set-up"));
+    e = hipEventRecord(p->done, s);
+    if (e != hipSuccess) return bail(hip_fail(e, "event"));
+    *out = p;
+    return EL_OK;
+}
+
+el_status el_plan_destroy(el_plan p) {
+    if (!p) return EL_OK;
+    if (p->done) (void)hipEventDestroy(p->done);
+    delete p;
+    return EL_OK;
+}
+
+el_status el_forward(el_plan p, const void *p0, double *traces, void *stream) {
+    el_status st = check_plan(p);
+    if (st != EL_OK) return st;
+    if (!p0 || (!traces && p->nrec > 0)) return fail(EL_EINVAL, "p0 or traces is NULL");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    HIP_TRY(hipStreamWaitEvent(s, p->done, 0), "order after the previous operation");
+    st = p->g.precision == EL_F64 ? run_forward(p, p->dd, static_cast<const double *>(p0), traces, s)
+                                  : run_forward(p, p->df, static_cast<const float *>(p0), traces, s);
+    if (st != EL_OK) return st;
+    HIP_TRY(hipEventRecord(p->done, s), "record completion");
+    return EL_OK;
+}
+
+el_status el_adjoint(el_plan p, const double *y, void *p_adj, void *stream) {
+    el_status st = check_plan(p);
+    if (st != EL_OK) return st;
+    if ((!y && p->nrec > 0) || !p_adj) return fail(EL_EINVAL, "y or p_adj is NULL");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    HIP_TRY(hipStreamWaitEvent(s, p->done, 0), "order after the previous operation");
+    st = p->g.precision == EL_F64 ? run_adjoint(p, p->dd, y, static_cast<double *>(p_adj), s)
+                                  : run_adjoint(p, p->df, y, static_cast<float *>(p_adj), s);
+    if (st != EL_OK) return st;
+    HIP_TRY(hipEventRecord(p->done, s), "record completion");
+    return EL_OK;
+}
+
+el_status el_dot_f64(el_plan p, int32_t space, const void *a, const void *b, double *out, void *stream) {
+    el_status st = check_plan(p);
+    if (st != EL_OK) return st;
+    if (!a || !b || !out) return fail(EL_EINVAL, "a, b or out is NULL");
+    if (space != 0 && space != 1) return fail(EL_EINVAL, "space must be 0 (N) or 1 (LM)");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    HIP_TRY(hipStreamWaitEvent(s, p->done, 0), "order after the previous operation");
+    double *partial = reinterpret_cast<double *>(p->ws + p->L.partial);
+    hipError_t e;
+    if (space == 1)
+        e = launch_dot(static_cast<const double *>(a), static_cast<const double *>(b),
+                       (long long)p->g.nsteps * p->nrec, partial, out, s);
+    else if (p->g.precision == EL_F64)
+        e = launch_dot(static_cast<const double *>(a), static_cast<const double *>(b), p->N, partial, out, s);
+    else
+        e = launch_dot(static_cast<const float *>(a), static_cast<const float *>(b), p->N, partial, out, s);
+    if (e != hipSuccess) return hip_fail(e, "dot");
+    HIP_TRY(hipEventRecord(p->done, s), "record completion");
+    return EL_OK;
+}
+
+el_status el_plan_field(el_plan p, int32_t id, void **ptr, size_t *count) {
+    if (!p) return fail(EL_EINVAL, "plan is NULL");
+    if (id < 0 || id >= NFIELD) return fail(EL_EINVAL, "field id %d outside 0..8", id);
+    if (!ptr || !count) return fail(EL_EINVAL, "ptr or count is NULL");
+    *ptr = p->ws + p->L.field[id];
+    *count = (size_t)p->N;
+    return EL_OK;
+}
+
+el_status el_plan_sizes(el_plan p, int64_t *ncells, int32_t *nrec, int32_t *nsteps) {
+    if (!p) return fail(EL_EINVAL, "plan is NULL");
+    if (ncells) *ncells = p->N;
+    if (nrec) *nrec = p->nrec;
+    if (nsteps) *nsteps = p->g.nsteps;
+    return EL_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,217 @@
+"""Python binding of the elastic operator library (ctypes over libel.so).
+
+Argument marshalling only: every step of H and H^T runs in the HIP kernels
+behind include/el.h.  PyTorch supplies device memory (the caller-owned
+workspace, inputs and outputs) and the stream.  If libel.so is missing the
+import of this module's functions raises; there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libel.so")
+
+EL_OK, EL_EINVAL, EL_EUNSTABLE, EL_ERANGE, EL_ENOMEM, EL_EDEVICE = 0, -1, -2, -3, -4, -5
+EL_F32, EL_F64 = 0, 1
+FIELDS = ("u1", "u2", "u3", "s11", "s22", "s33", "s23", "s13", "s12")
+
+
+class ElError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{status_name(status)}: {msg}")
+        self.status = status
+
+
+class Grid(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("dx", ctypes.c_double), ("dt", ctypes.c_double),
+                ("nsteps", ctypes.c_int32), ("npml", ctypes.c_int32),
+                ("pml_R", ctypes.c_double), ("pml_npower", ctypes.c_double), ("pml_f0", ctypes.c_double),
+                ("precision", ctypes.c_int32)]
+
+
+_lib = None
+EXPORTS = ("el_version", "el_status_string", "el_last_error", "el_grid_check", "el_plan_bytes",
+           "el_plan_create", "el_plan_destroy", "el_forward", "el_adjoint", "el_dot_f64",
+           "el_plan_field", "el_plan_sizes")
+
+
+def lib():
+    """Load libel.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_1709_02733_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, st = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32
+        L.el_version.restype = ctypes.c_char_p
+        L.el_status_string.restype = ctypes.c_char_p
+        L.el_status_string.argtypes = [st]
+        L.el_last_error.restype = ctypes.c_char_p
+        L.el_grid_check.restype = st
+        L.el_grid_check.argtypes = [ctypes.POINTER(Grid), vp, i32]
+        L.el_plan_bytes.restype = st
+        L.el_plan_bytes.argtypes = [ctypes.POINTER(Grid), i32, ctypes.POINTER(ctypes.c_size_t)]
+        L.el_plan_create.restype = st
+        L.el_plan_create.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(Grid), vp, vp, vp, vp, vp, i32,
+                                     vp, ctypes.c_size_t, vp]
+        L.el_plan_destroy.restype = st
+        L.el_plan_destroy.argtypes = [vp]
+        L.el_forward.restype = st
+        L.el_forward.argtypes = [vp, vp, vp, vp]
+        L.el_adjoint.restype = st
+        L.el_adjoint.argtypes = [vp, vp, vp, vp]
+        L.el_dot_f64.restype = st
+        L.el_dot_f64.argtypes = [vp, i32, vp, vp, vp, vp]
+        L.el_plan_field.restype = st
+        L.el_plan_field.argtypes = [vp, i32, ctypes.POINTER(vp), ctypes.POINTER(ctypes.c_size_t)]
+        L.el_plan_sizes.restype = st
+        L.el_plan_sizes.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(i32), ctypes.POINTER(i32)]
+        _lib = L
+    return _lib
+
+
+def status_name(s: int) -> str:
+    try:
+        return lib().el_status_string(s).decode()
+    except RuntimeError:
+        return str(s)
+
+
+def _check(status: int):
+    if status != EL_OK:
+        raise ElError(status, lib().el_last_error().decode())
+
+
+def version() -> str:
+    return lib().el_version().decode()
+
+
+def make_grid(nx, ny, nz, dx, dt, nsteps, npml, precision="f32", pml_R=0.0, pml_npower=0.0, pml_f0=0.0) -> Grid:
+    prec = {"f32": EL_F32, "f64": EL_F64}[precision] if isinstance(precision, str) else int(precision)
+    return Grid(int(nx), int(ny), int(nz), float(dx), float(dt), int(nsteps), int(npml),
+                float(pml_R), float(pml_npower), float(pml_f0), prec)
+
+
+def grid_check(grid: Grid, rec=None) -> None:
+    r = None if rec is None else np.ascontiguousarray(rec, dtype=np.float64).reshape(-1, 3)
+    n = 0 if r is None else r.shape[0]
+    _check(lib().el_grid_check(ctypes.byref(grid), None if r is None else r.ctypes.data_as(ctypes.c_void_p), n))
+
+
+def plan_bytes(grid: Grid, nrec: int) -> int:
+    out = ctypes.c_size_t(0)
+    _check(lib().el_plan_bytes(ctypes.byref(grid), int(nrec), ctypes.byref(out)))
+    return int(out.value)
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _dev_f32(a, device):
+    t = torch.as_tensor(a)
+    return t.to(device=device, dtype=torch.float32).contiguous()
+
+
+class Plan:
+    """One grid, medium and receiver set on one GPU; applies H and H^T.
+
+    lam, mu, rho, alpha: cell maps [nz][ny][nx] (numpy or torch); they are
+    copied into the plan's workspace.  rec: [L][3] receiver positions in
+    metres from the centre of cell (0,0,0).
+    """
+
+    def __init__(self, nx, ny, nz, dx, dt, nsteps, npml, lam, mu, rho, alpha, rec,
+                 precision="f32", pml_R=0.0, pml_npower=0.0, pml_f0=0.0, device=None, stream=None):
+        L = lib()
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.grid = make_grid(nx, ny, nz, dx, dt, nsteps, npml, precision, pml_R, pml_npower, pml_f0)
+        self.precision = "f64" if self.grid.precision == EL_F64 else "f32"
+        self.dtype = torch.float64 if self.precision == "f64" else torch.float32
+        self.shape = (int(nz), int(ny), int(nx))
+        self.N = int(nx) * int(ny) * int(nz)
+        self.nsteps = int(nsteps)
+        rec = np.ascontiguousarray(np.asarray(rec, dtype=np.float64).reshape(-1, 3))
+        self.nrec = rec.shape[0]
+        self._rec = rec
+        self.bytes = plan_bytes(self.grid, self.nrec)
+        with torch.cuda.device(self.device):
+            self.workspace = torch.empty(self.bytes, dtype=torch.uint8, device=self.device)
+            maps = [_dev_f32(m, self.device) for m in (lam, mu, rho, alpha)]
+            for m in maps:
+                assert m.numel() == self.N, "material map size does not match the grid"
+            h = ctypes.c_void_p(None)
+            st = L.el_plan_create(ctypes.byref(h), ctypes.byref(self.grid),
+                                  *[ctypes.c_void_p(m.data_ptr()) for m in maps],
+                                  rec.ctypes.data_as(ctypes.c_void_p), self.nrec,
+                                  ctypes.c_void_p(self.workspace.data_ptr()), self.bytes, _stream(stream))
+            _check(st)
+        self._h = h
+
+    @classmethod
+    def from_scenario(cls, sc, precision="f32", **kw):
+        return cls(sc.nx, sc.ny, sc.nz, sc.dx, sc.dt, sc.nsteps, sc.npml, sc.lam, sc.mu, sc.rho,
+                   sc.alpha, sc.rec, precision=precision, **kw)
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            lib().el_plan_destroy(h)
+        self._h = None
+
+    __del__ = close
+
+    # ----------------------------------------------------------- operators
+    def forward(self, p0, out=None, stream=None) -> torch.Tensor:
+        """traces[M][L] (float64, device) = H p0."""
+        p = torch.as_tensor(p0).to(device=self.device, dtype=self.dtype).contiguous()
+        assert p.numel() == self.N
+        if out is None:
+            out = torch.empty((self.nsteps, self.nrec), dtype=torch.float64, device=self.device)
+        assert out.dtype == torch.float64 and out.is_contiguous() and out.numel() == self.nsteps * self.nrec
+        with torch.cuda.device(self.device):
+            _check(lib().el_forward(self._h, ctypes.c_void_p(p.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                    _stream(stream)))
+        return out
+
+    def adjoint(self, y, out=None, stream=None) -> torch.Tensor:
+        """p_adj[nz][ny][nx] (plan precision, device) = H^T y."""
+        yy = torch.as_tensor(y).to(device=self.device, dtype=torch.float64).contiguous()
+        assert yy.numel() == self.nsteps * self.nrec
+        if out is None:
+            out = torch.empty(self.shape, dtype=self.dtype, device=self.device)
+        assert out.dtype == self.dtype and out.is_contiguous() and out.numel() == self.N
+        with torch.cuda.device(self.device):
+            _check(lib().el_adjoint(self._h, ctypes.c_void_p(yy.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                    _stream(stream)))
+        return out
+
+    def dot(self, a, b, space: int, stream=None) -> torch.Tensor:
+        """<a, b> in float64 on the device; space 0 = volume (plan precision), 1 = traces."""
+        dt = self.dtype if space == 0 else torch.float64
+        aa = torch.as_tensor(a).to(device=self.device, dtype=dt).contiguous()
+        bb = torch.as_tensor(b).to(device=self.device, dtype=dt).contiguous()
+        out = torch.empty((), dtype=torch.float64, device=self.device)
+        with torch.cuda.device(self.device):
+            _check(lib().el_dot_f64(self._h, int(space), ctypes.c_void_p(aa.data_ptr()),
+                                    ctypes.c_void_p(bb.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                    _stream(stream)))
+        return out
+
+    def field(self, name) -> torch.Tensor:
+        """View of one of the plan's wavefield arrays (u1..s12) inside the workspace."""
+        fid = FIELDS.index(name) if isinstance(name, str) else int(name)
+        ptr = ctypes.c_void_p(None)
+        cnt = ctypes.c_size_t(0)
+        _check(lib().el_plan_field(self._h, fid, ctypes.byref(ptr), ctypes.byref(cnt)))
+        off = ptr.value - self.workspace.data_ptr()
+        es = 8 if self.precision == "f64" else 4
+        return self.workspace[off:off + cnt.value * es].view(self.dtype).view(self.shape)

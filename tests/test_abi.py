@@ -1,0 +1,79 @@
+"""The C ABI library loads, exports every symbol include/el.h declares, and its
+host-only logic (grid checks, workspace sizing) behaves as documented.  No
+GPU is touched."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1709_02733_amd import el
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "el.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(el_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_header_symbols_exported():
+    L = el.lib()
+    names = _declared()
+    assert "el_forward" in names and "el_adjoint" in names and "el_plan_create" in names
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(el.EXPORTS)
+
+
+def test_version_and_status_strings():
+    assert "gfx950" in el.version()
+    assert el.status_name(el.EL_ERANGE) == "EL_ERANGE"
+    assert el.status_name(-77) == "EL_UNKNOWN"
+
+
+def _g(**kw):
+    base = dict(nx=16, ny=12, nz=10, dx=1e-4, dt=1e-8, nsteps=10, npml=3)
+    base.update(kw)
+    prec = base.pop("precision", "f32")
+    return el.make_grid(precision=prec, **base)
+
+
+@pytest.mark.parametrize("bad,code", [
+    (dict(nx=3), el.EL_EINVAL), (dict(dx=0.0), el.EL_EINVAL), (dict(dt=-1.0), el.EL_EINVAL),
+    (dict(nsteps=0), el.EL_EINVAL), (dict(npml=-1), el.EL_EINVAL), (dict(npml=5), el.EL_EINVAL),
+    (dict(precision=7), el.EL_EINVAL), (dict(dx=float("nan")), el.EL_EINVAL),
+])
+def test_grid_check_rejects(bad, code):
+    with pytest.raises(el.ElError) as ei:
+        el.grid_check(_g(**bad))
+    assert ei.value.status == code
+
+
+def test_grid_check_receivers():
+    g = _g()
+    dx = g.dx
+    el.grid_check(g, np.array([[0, 0, 0], [15, 11, 9], [7.5, 3.25, 0.0]]) * dx)
+    for bad in ([[15.0001, 1, 1]], [[1, -0.01, 1]], [[1, 1, 9.5]]):
+        with pytest.raises(el.ElError) as ei:
+            el.grid_check(g, np.array(bad) * dx)
+        assert ei.value.status == el.EL_ERANGE
+    # npml = 2*P+2 boundary is accepted, one less is not
+    el.grid_check(_g(nx=8, ny=8, nz=8, npml=3))
+    with pytest.raises(el.ElError):
+        el.grid_check(_g(nx=7, ny=8, nz=8, npml=3))
+
+
+def test_plan_bytes_scales_with_precision_and_grid():
+    b32 = el.plan_bytes(_g(), 5)
+    b64 = el.plan_bytes(_g(precision="f64"), 5)
+    N = 16 * 12 * 10
+    # 9 fields + 4 maps dominate; doubles take twice the bytes
+    assert b32 >= 13 * N * 4
+    assert b64 >= 13 * N * 8
+    assert b64 > b32
+    assert el.plan_bytes(_g(npml=0), 5) < b32
+    big = el.make_grid(384, 384, 384, 1e-4, 1e-8, 2500, 16)
+    nb = el.plan_bytes(big, 1024)
+    assert 13 * 384 ** 3 * 4 < nb < 16 * 384 ** 3 * 4

@@ -163,8 +163,28 @@ el_status el_dot_f64(el_plan plan, int32_t space, const void *a, const void *b, 
  */
 el_status el_plan_field(el_plan plan, int32_t id, void **ptr, size_t *count);
 
-/* Number of cells N and of receivers L of a plan. */
+/* Number of cells N, receivers L and trace samples M of a plan. */
 el_status el_plan_sizes(el_plan plan, int64_t *ncells, int32_t *nrec, int32_t *nsteps);
+
+/* Kernel kinds reported by el_plan_kernel_time(). */
+#define EL_K_VELOCITY     0   /* forward velocity pass (+ phi slabs)           */
+#define EL_K_STRESS       1   /* forward stress pass (+ psi slabs)             */
+#define EL_K_ADJ_VELOCITY 2   /* adjoint pass producing the velocity adjoint   */
+#define EL_K_ADJ_STRESS   3   /* adjoint pass producing the stress adjoint     */
+#define EL_K_GATHER       4   /* receiver gather (forward)                     */
+#define EL_K_SCATTER      5   /* receiver scatter (adjoint)                    */
+#define EL_K_COUNT        6
+
+/*
+ * Benchmark instrumentation.  With enable = 1, every kernel launch of the
+ * time loops of later el_forward / el_adjoint calls is bracketed by a pair
+ * of HIP events recorded on that call's stream; enable = 0 stops recording.
+ * el_plan_kernel_time() waits for the recorded events, returns how many
+ * launches of one kind were recorded and their summed duration in ms, and
+ * clears the record of that kind.  Host-blocking; not for production loops.
+ */
+el_status el_plan_timing(el_plan plan, int32_t enable);
+el_status el_plan_kernel_time(el_plan plan, int32_t kind, int64_t *launches, double *total_ms);
 
 #ifdef __cplusplus
 }

@@ -1,0 +1,49 @@
+"""Algorithmic HBM bytes of each kernel of the time loops.
+
+Every input array a kernel needs is counted as read once and every array it
+produces as written once (the minimum traffic of the algorithm, with the
+staggered-grid averages of rho, alpha and mu formed on chip from the four
+cell maps).  Memory variables of the C-PML live only on the 2*npml planes of
+each axis where the layer coefficient a is non-zero.
+
+Per cell of the volume (es = bytes per element, 4 for float):
+  velocity      reads s x6, u x3, rho, alpha;   writes u x3     -> 14 es
+  stress        reads u x3, s x6, lambda, mu;   writes s x6     -> 17 es
+  adj_velocity  reads s x6, q x3, lambda, mu, alpha; writes q x3 -> 15 es
+  adj_stress    reads q x3, s x6, rho;          writes s x6     -> 16 es
+Per C-PML cell of each axis:
+  velocity / stress          phi (psi) x3 read + x3 written        ->  6 es
+  adj_velocity / adj_stress  psi~ (phi~) x3 read, phi~ (psi~) x3 read + written -> 9 es
+Receivers: gather 24 + 8 + 8 bytes per (receiver, corner) plus 8 per trace
+sample; scatter the same per entry.
+"""
+from __future__ import annotations
+
+PER_CELL = {"velocity": 14, "stress": 17, "adj_velocity": 15, "adj_stress": 16}
+PER_PML_CELL = {"velocity": 6, "stress": 6, "adj_velocity": 9, "adj_stress": 9}
+
+
+def pml_cells(nx: int, ny: int, nz: int, npml: int) -> int:
+    """Cells of the C-PML summed over the three axes (2*npml planes each)."""
+    if npml <= 0:
+        return 0
+    return 2 * npml * (ny * nz + nx * nz + nx * ny)
+
+
+def kernel_bytes(kind: str, nx: int, ny: int, nz: int, npml: int, nrec: int, es: int = 4) -> float:
+    """Algorithmic bytes of one launch of a kernel kind."""
+    N = nx * ny * nz
+    if kind in PER_CELL:
+        return float(N * PER_CELL[kind] * es + pml_cells(nx, ny, nz, npml) * PER_PML_CELL[kind] * es)
+    if kind in ("gather", "scatter"):
+        return float(nrec * 8 * (3 * es + 16) + nrec * 8)
+    raise KeyError(kind)
+
+
+def step_bytes(op: str, nx, ny, nz, npml, nrec, es=4) -> float:
+    """Bytes of one time step of the forward ('fwd') or adjoint ('adj') operator."""
+    if op == "fwd":
+        ks = ("velocity", "stress", "gather")
+    else:
+        ks = ("adj_velocity", "adj_stress", "scatter")
+    return sum(kernel_bytes(k, nx, ny, nz, npml, nrec, es) for k in ks)

@@ -57,8 +57,13 @@ struct el_plan_ {
     Dev<float> df;
     Dev<double> dd;
     Rec rec;
+    Tiles tiles;
     hipEvent_t done;
     double cmax;
+    // benchmark instrumentation: per kernel kind, event pairs and how many are in use
+    bool timing = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[EL_K_COUNT];
+    size_t used[EL_K_COUNT] = {};
 };
 
 namespace el {
@@ -96,6 +101,24 @@ bool layout(const el_grid &g, int nrec, Layout *L) {
     L->partial = take(7 * kDotBlocks * 8);
     L->total = off;
     return true;
+}
+
+// Tiles of kTileX x kTileY columns; the z extent is cut into chunks so that the grid holds
+// about 2048 tiles (at least 4, at most 64 planes per chunk), and the grid is padded to a
+// multiple of 8 blocks so that block b % 8 (its XCD) owns tiles [x * per, (x + 1) * per).
+Tiles make_tiles(int nx, int ny, int nz) {
+    Tiles t;
+    t.ntx = (nx + kTileX - 1) / kTileX;
+    t.nty = (ny + kTileY - 1) / kTileY;
+    const long long cols = (long long)t.ntx * t.nty;
+    int target = (int)((cols * nz + 2047) / 2048);
+    target = std::max(4, std::min(64, target));
+    t.nzc = (nz + target - 1) / target;
+    t.zc = (nz + t.nzc - 1) / t.nzc;
+    t.nzc = (nz + t.zc - 1) / t.zc;
+    t.ntiles = t.ntx * t.nty * t.nzc;
+    t.per = (t.ntiles + 7) / 8;
+    return t;
 }
 
 }  // namespace el
@@ -309,16 +332,38 @@ el_status check_plan(el_plan p) {
     return EL_OK;
 }
 
+// Launch one kernel of the time loops, bracketed by an event pair when timing is on.
+template <typename F>
+hipError_t timed(el_plan p, int kind, hipStream_t s, F launch) {
+    if (!p->timing) return launch();
+    auto &v = p->ev[kind];
+    if (p->used[kind] == v.size()) {
+        hipEvent_t a, b;
+        hipError_t e = hipEventCreate(&a);
+        if (e != hipSuccess) return e;
+        e = hipEventCreate(&b);
+        if (e != hipSuccess) return e;
+        v.emplace_back(a, b);
+    }
+    auto &pr = v[p->used[kind]++];
+    hipError_t e = hipEventRecord(pr.first, s);
+    if (e != hipSuccess) return e;
+    e = launch();
+    if (e != hipSuccess) return e;
+    return hipEventRecord(pr.second, s);
+}
+
 template <typename T>
 el_status run_forward(el_plan p, Dev<T> &d, const T *p0, double *traces, hipStream_t s) {
     const int M = p->g.nsteps, L = p->nrec;
     HIP_TRY(launch_zero_state(d, s), "zero state");
     HIP_TRY(launch_inject(d, p0, s), "inject");
-    HIP_TRY(launch_gather(d, p->rec, traces, s), "gather");
+    HIP_TRY(timed(p, EL_K_GATHER, s, [&] { return launch_gather(d, p->rec, traces, s); }), "gather");
     for (int m = 1; m < M; ++m) {
-        HIP_TRY(launch_velocity(d, s), "velocity pass");
-        HIP_TRY(launch_stress(d, s), "stress pass");
-        HIP_TRY(launch_gather(d, p->rec, traces + (size_t)m * L, s), "gather");
+        HIP_TRY(timed(p, EL_K_VELOCITY, s, [&] { return launch_velocity(d, p->tiles, s); }), "velocity pass");
+        HIP_TRY(timed(p, EL_K_STRESS, s, [&] { return launch_stress(d, p->tiles, s); }), "stress pass");
+        HIP_TRY(timed(p, EL_K_GATHER, s, [&] { return launch_gather(d, p->rec, traces + (size_t)m * L, s); }),
+                "gather");
     }
     return EL_OK;
 }
@@ -327,11 +372,14 @@ template <typename T>
 el_status run_adjoint(el_plan p, Dev<T> &d, const double *y, T *out, hipStream_t s) {
     const int M = p->g.nsteps, L = p->nrec;
     HIP_TRY(launch_zero_state(d, s), "zero state");
-    HIP_TRY(launch_scatter(d, p->rec, y + (size_t)(M - 1) * L, s), "scatter");
+    HIP_TRY(timed(p, EL_K_SCATTER, s, [&] { return launch_scatter(d, p->rec, y + (size_t)(M - 1) * L, s); }),
+            "scatter");
     for (int m = M - 1; m >= 1; --m) {
-        HIP_TRY(launch_adj_velocity(d, s), "adjoint velocity pass");
-        HIP_TRY(launch_adj_stress(d, s), "adjoint stress pass");
-        HIP_TRY(launch_scatter(d, p->rec, y + (size_t)(m - 1) * L, s), "scatter");
+        HIP_TRY(timed(p, EL_K_ADJ_VELOCITY, s, [&] { return launch_adj_velocity(d, p->tiles, s); }),
+                "adjoint velocity pass");
+        HIP_TRY(timed(p, EL_K_ADJ_STRESS, s, [&] { return launch_adj_stress(d, p->tiles, s); }), "adjoint stress pass");
+        HIP_TRY(timed(p, EL_K_SCATTER, s, [&] { return launch_scatter(d, p->rec, y + (size_t)(m - 1) * L, s); }),
+                "scatter");
     }
     HIP_TRY(launch_extract(d, out, s), "extract");
     return EL_OK;
@@ -366,6 +414,7 @@ el_status el_plan_create(el_plan *out, const el_grid *grid, const float *lam, co
     p->L = L;
     p->ws = static_cast<char *>(workspace);
     p->device = dev;
+    p->tiles = make_tiles(grid->nx, grid->ny, grid->nz);
     auto bail = [&](el_status e) {
         if (p->done) (void)hipEventDestroy(p->done);
         delete p;
@@ -419,7 +468,36 @@ el_status el_plan_create(el_plan *out, const el_grid *grid, const float *lam, co
 el_status el_plan_destroy(el_plan p) {
     if (!p) return EL_OK;
     if (p->done) (void)hipEventDestroy(p->done);
+    for (auto &v : p->ev)
+        for (auto &pr : v) {
+            (void)hipEventDestroy(pr.first);
+            (void)hipEventDestroy(pr.second);
+        }
     delete p;
+    return EL_OK;
+}
+
+el_status el_plan_timing(el_plan p, int32_t enable) {
+    if (!p) return fail(EL_EINVAL, "plan is NULL");
+    p->timing = enable != 0;
+    return EL_OK;
+}
+
+el_status el_plan_kernel_time(el_plan p, int32_t kind, int64_t *launches, double *total_ms) {
+    if (!p) return fail(EL_EINVAL, "plan is NULL");
+    if (kind < 0 || kind >= EL_K_COUNT) return fail(EL_EINVAL, "kernel kind %d outside 0..%d", kind, EL_K_COUNT - 1);
+    double ms = 0.0;
+    const size_t n = p->used[kind];
+    for (size_t q = 0; q < n; ++q) {
+        auto &pr = p->ev[kind][q];
+        HIP_TRY(hipEventSynchronize(pr.second), "wait for timing event");
+        float t = 0.f;
+        HIP_TRY(hipEventElapsedTime(&t, pr.first, pr.second), "elapsed time");
+        ms += t;
+    }
+    p->used[kind] = 0;
+    if (launches) *launches = (int64_t)n;
+    if (total_ms) *total_ms = ms;
     return EL_OK;
 }
 

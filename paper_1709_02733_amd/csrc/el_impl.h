@@ -32,6 +32,16 @@ struct Dev {
                              //   mem[j][3 + i] = psi^{ij} (sigma^{ij} point)
 };
 
+// Column tiles of the stencil passes: kTileX x kTileY cells in x-y, a chunk of zc planes in z.
+constexpr int kTileX = 64;
+constexpr int kTileY = 8;
+struct Tiles {
+    int ntx, nty, nzc, zc;   // tiles along x and y, z chunks, planes per chunk
+    int ntiles;              // ntx * nty * nzc
+    int per;                 // tiles per XCD: the grid has 8 * per blocks
+};
+Tiles make_tiles(int nx, int ny, int nz);
+
 // Receiver tables.
 struct Rec {
     int nrec;
@@ -68,11 +78,11 @@ hipError_t launch_media_stats(const float *lam, const float *mu, const float *rh
                               long long n, double dt, double *stats, double *partial, hipStream_t s);
 template <typename T> hipError_t launch_zero_state(const Dev<T> &d, hipStream_t s);
 template <typename T> hipError_t launch_inject(const Dev<T> &d, const T *p0, hipStream_t s);
-template <typename T> hipError_t launch_velocity(const Dev<T> &d, hipStream_t s);
-template <typename T> hipError_t launch_stress(const Dev<T> &d, hipStream_t s);
+template <typename T> hipError_t launch_velocity(const Dev<T> &d, const Tiles &tl, hipStream_t s);
+template <typename T> hipError_t launch_stress(const Dev<T> &d, const Tiles &tl, hipStream_t s);
 template <typename T> hipError_t launch_gather(const Dev<T> &d, const Rec &r, double *trace_row, hipStream_t s);
-template <typename T> hipError_t launch_adj_velocity(const Dev<T> &d, hipStream_t s);
-template <typename T> hipError_t launch_adj_stress(const Dev<T> &d, hipStream_t s);
+template <typename T> hipError_t launch_adj_velocity(const Dev<T> &d, const Tiles &tl, hipStream_t s);
+template <typename T> hipError_t launch_adj_stress(const Dev<T> &d, const Tiles &tl, hipStream_t s);
 template <typename T> hipError_t launch_scatter(const Dev<T> &d, const Rec &r, const double *y_row, hipStream_t s);
 template <typename T> hipError_t launch_extract(const Dev<T> &d, T *p, hipStream_t s);
 template <typename T> hipError_t launch_dot(const T *a, const T *b, long long n, double *partial, double *out,

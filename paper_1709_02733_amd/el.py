@@ -38,7 +38,8 @@ class Grid(ctypes.Structure):
 _lib = None
 EXPORTS = ("el_version", "el_status_string", "el_last_error", "el_grid_check", "el_plan_bytes",
            "el_plan_create", "el_plan_destroy", "el_forward", "el_adjoint", "el_dot_f64",
-           "el_plan_field", "el_plan_sizes")
+           "el_plan_field", "el_plan_sizes", "el_plan_timing", "el_plan_kernel_time")
+KERNELS = ("velocity", "stress", "adj_velocity", "adj_stress", "gather", "scatter")
 
 
 def lib():
@@ -72,6 +73,10 @@ def lib():
         L.el_plan_field.argtypes = [vp, i32, ctypes.POINTER(vp), ctypes.POINTER(ctypes.c_size_t)]
         L.el_plan_sizes.restype = st
         L.el_plan_sizes.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(i32), ctypes.POINTER(i32)]
+        L.el_plan_timing.restype = st
+        L.el_plan_timing.argtypes = [vp, i32]
+        L.el_plan_kernel_time.restype = st
+        L.el_plan_kernel_time.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)]
         _lib = L
     return _lib
 
@@ -204,6 +209,20 @@ class Plan:
             _check(lib().el_dot_f64(self._h, int(space), ctypes.c_void_p(aa.data_ptr()),
                                     ctypes.c_void_p(bb.data_ptr()), ctypes.c_void_p(out.data_ptr()),
                                     _stream(stream)))
+        return out
+
+    def timing(self, enable: bool = True):
+        """Record an event pair around every time-loop kernel launch of later operations."""
+        _check(lib().el_plan_timing(self._h, 1 if enable else 0))
+
+    def kernel_times(self) -> dict:
+        """{kernel: (launches, total_ms)} recorded since the last call (host-blocking)."""
+        out = {}
+        for k, name in enumerate(KERNELS):
+            n = ctypes.c_int64(0)
+            ms = ctypes.c_double(0.0)
+            _check(lib().el_plan_kernel_time(self._h, k, ctypes.byref(n), ctypes.byref(ms)))
+            out[name] = (int(n.value), float(ms.value))
         return out
 
     def field(self, name) -> torch.Tensor:

@@ -188,3 +188,48 @@ def test_plan_rejects_unstable_and_invalid_media():
     # the plan still works after rejected attempts
     plan = _plan(sc)
     assert torch.isfinite(plan.forward(torch.from_numpy(sc.p0))).all()
+
+
+# ------------------------------------------------------- full-size (384^3)
+
+@pytest.fixture(scope="module")
+def skull384():
+    return S.make("skull384", nsteps=4)
+
+
+def test_full_size_state_and_traces(skull384):
+    """384^3 skull medium in the benchmark's launch configuration: after 3 updates every
+    wavefield array and the 4 trace samples match the FP64 oracle."""
+    sc = skull384
+    plan = el.Plan.from_scenario(sc)
+    tr = plan.forward(torch.from_numpy(sc.p0)).cpu().numpy()
+    fields = {n: plan.field(n).cpu().numpy() for n in el.FIELDS}
+    del plan
+    torch.cuda.empty_cache()
+    ref = Model.from_scenario(sc)
+    v = ref.inject(sc.p0.astype(np.float64))
+    tr_ref = [ref.measure(v)]
+    for _ in range(sc.nsteps - 1):
+        ref.step(v)
+        tr_ref.append(ref.measure(v))
+    tr_ref = np.array(tr_ref)
+    sv = ref.state_views(v)
+    refs = dict(zip(el.FIELDS, list(sv["u"]) + list(sv["sig"])))
+    for n in el.FIELDS:
+        e = rel_max(fields[n], refs[n])
+        banner(f"384^3 field {n}: rel max err {e:.2e}")
+        assert e <= 1e-5, (n, e)
+    assert rel_max(tr, tr_ref) <= 1e-5
+
+
+def test_full_size_adjoint(skull384):
+    sc = skull384
+    plan = el.Plan.from_scenario(sc)
+    y = np.random.default_rng(4).standard_normal((sc.nsteps, sc.nrec))
+    pa = plan.adjoint(torch.from_numpy(y)).cpu().numpy().astype(np.float64)
+    del plan
+    torch.cuda.empty_cache()
+    pa_ref = Model.from_scenario(sc).adjoint(y)
+    e = rel_max(pa, pa_ref)
+    banner(f"384^3 adjoint rel max err {e:.2e}, rel L2 {rel_l2(pa, pa_ref):.2e}")
+    assert e <= 1e-5

@@ -158,10 +158,20 @@ el_status el_dot_f64(el_plan plan, int32_t space, const void *a, const void *b, 
  * Device pointer and element count of one of the plan's wavefield arrays,
  * for inspection after an operation has completed: id 0..2 = u1, u2, u3;
  * 3..8 = s11, s22, s33, s23, s13, s12 (elements of the plan's precision).
- * After el_forward they hold u_{M-3/2} and sigma_{M-1}; after el_adjoint
- * they hold the adjoint state of step 0.
+ * The arrays are stored padded (see el_plan_layout); *count is the padded
+ * element count.  After el_forward they hold u_{M-3/2} and sigma_{M-1};
+ * after el_adjoint they hold the adjoint state of step 0 in the variables
+ * r = Q^{-1} q (ids 0..2, the velocity adjoint divided by the staggered
+ * density) and w = C s (ids 3..8, the Voigt stiffness applied to the stress
+ * adjoint).
  */
 el_status el_plan_field(el_plan plan, int32_t id, void **ptr, size_t *count);
+
+/*
+ * Padded layout of the wavefield arrays: cell (i, j, k) is element
+ * origin + k * plane_pitch + j * row_pitch + i.  The padding holds zeros.
+ */
+el_status el_plan_layout(el_plan plan, int64_t *row_pitch, int64_t *plane_pitch, int64_t *origin);
 
 /* Number of cells N, receivers L and trace samples M of a plan. */
 el_status el_plan_sizes(el_plan plan, int64_t *ncells, int32_t *nrec, int32_t *nsteps);

@@ -68,9 +68,22 @@ struct el_plan_ {
 
 namespace el {
 
+Vol make_vol(int nx, int ny, int nz) {
+    Vol v;
+    v.nx = nx;
+    v.ny = ny;
+    v.nz = nz;
+    v.px = (nx + 2 + 31) / 32 * 32;
+    v.py = ny + 2;
+    v.plane = (long long)v.px * v.py;
+    v.total = v.plane * (nz + 4);
+    v.origin = 2 * v.plane;
+    return v;
+}
+
 bool layout(const el_grid &g, int nrec, Layout *L) {
     const size_t es = g.precision == EL_F64 ? 8 : 4;
-    const size_t N = (size_t)g.nx * g.ny * g.nz;
+    const size_t N = (size_t)make_vol(g.nx, g.ny, g.nz).total;
     size_t off = 0;
     auto take = [&](size_t bytes) {
         size_t o = off;
@@ -80,7 +93,7 @@ bool layout(const el_grid &g, int nrec, Layout *L) {
     for (int f = 0; f < NFIELD; ++f) L->field[f] = take(N * es);
     for (int m = 0; m < 4; ++m) L->map[m] = take(N * es);
     const int P = g.npml;
-    const size_t W = P > 0 ? 2 * (size_t)(P + 1) : 0;
+    const size_t W = P > 0 ? 2 * (size_t)(P + 7) : 0;
     const size_t ns[3] = {W * g.ny * g.nz, (size_t)g.nx * W * g.nz, (size_t)g.nx * g.ny * W};
     const int n[3] = {g.nx, g.ny, g.nz};
     for (int a = 0; a < 3; ++a)
@@ -94,6 +107,7 @@ bool layout(const el_grid &g, int nrec, Layout *L) {
     L->rec_idx = take(E * 8);
     L->rec_w = take(E * 8);
     L->csr_pt = take(E * 8);
+    L->csr_ptc = take(E * 3 * 4);
     L->csr_row = take((E + 1) * 4);
     L->csr_rec = take(E * 4);
     L->csr_w = take(E * 8);
@@ -103,16 +117,17 @@ bool layout(const el_grid &g, int nrec, Layout *L) {
     return true;
 }
 
-// Tiles of kTileX x kTileY columns; the z extent is cut into chunks so that the grid holds
-// about 2048 tiles (at least 4, at most 64 planes per chunk), and the grid is padded to a
-// multiple of 8 blocks so that block b % 8 (its XCD) owns tiles [x * per, (x + 1) * per).
+// Tiles of kTileX x kTileY columns; the z extent is cut into chunks of at most 16 planes
+// (fewer on small grids, down to 4, so that about 4096 tiles exist), and the grid is
+// padded to a multiple of 8 blocks so that block b % 8 (its XCD) owns tiles
+// [x * per, (x + 1) * per).
 Tiles make_tiles(int nx, int ny, int nz) {
     Tiles t;
     t.ntx = (nx + kTileX - 1) / kTileX;
     t.nty = (ny + kTileY - 1) / kTileY;
     const long long cols = (long long)t.ntx * t.nty;
-    int target = (int)((cols * nz + 2047) / 2048);
-    target = std::max(4, std::min(64, target));
+    int target = (int)((cols * nz + 4095) / 4096);
+    target = std::max(4, std::min(16, target));
     t.nzc = (nz + target - 1) / target;
     t.zc = (nz + t.nzc - 1) / t.nzc;
     t.nzc = (nz + t.zc - 1) / t.zc;
@@ -145,7 +160,6 @@ el_status el_grid_check(const el_grid *g, const double *rec, int32_t nrec) {
     if (!g) return fail(EL_EINVAL, "grid is NULL");
     if (g->nx < 4 || g->ny < 4 || g->nz < 4)
         return fail(EL_EINVAL, "grid %dx%dx%d: every axis needs at least 4 cells", g->nx, g->ny, g->nz);
-    if ((long long)g->nx * g->ny * g->nz > (1LL << 40)) return fail(EL_EINVAL, "grid too large");
     if (!(g->dx > 0) || !std::isfinite(g->dx)) return fail(EL_EINVAL, "dx must be positive and finite");
     if (!(g->dt > 0) || !std::isfinite(g->dt)) return fail(EL_EINVAL, "dt must be positive and finite");
     if (g->nsteps < 1) return fail(EL_EINVAL, "nsteps must be >= 1");
@@ -155,6 +169,13 @@ el_status el_grid_check(const el_grid *g, const double *rec, int32_t nrec) {
         if (g->npml > 0 && n[a] < 2 * g->npml + 2)
             return fail(EL_EINVAL, "axis %d has %d cells, fewer than 2*npml+2 = %d", a, n[a], 2 * g->npml + 2);
     if (g->precision != EL_F32 && g->precision != EL_F64) return fail(EL_EINVAL, "precision must be EL_F32 or EL_F64");
+    {
+        const long long es = g->precision == EL_F64 ? 8 : 4;
+        const long long bytes = make_vol(g->nx, g->ny, g->nz).total * es;
+        if (bytes >= (1LL << 32))
+            return fail(EL_EINVAL, "grid %dx%dx%d: one padded volume array needs %lld bytes; the kernels address at most 4 GiB per array",
+                        g->nx, g->ny, g->nz, bytes);
+    }
     if (nrec < 0) return fail(EL_EINVAL, "nrec must be >= 0");
     if (nrec > (1 << 26)) return fail(EL_EINVAL, "too many receivers");
     if (nrec > 0 && !rec) return fail(EL_EINVAL, "rec_xyz is NULL");
@@ -213,10 +234,15 @@ template <typename T>
 void bind(Dev<T> &d, el_plan_ *p) {
     const el_grid &g = p->g;
     char *ws = p->ws;
+    const Vol v = make_vol(g.nx, g.ny, g.nz);
     d.nx = g.nx;
     d.ny = g.ny;
     d.nz = g.nz;
-    d.nxy = (long long)g.nx * g.ny;
+    d.px = v.px;
+    d.plane = v.plane;
+    d.sy = (unsigned)(v.px * sizeof(T));
+    d.sz = (unsigned)(v.plane * sizeof(T));
+    d.origin = (unsigned)(v.origin * sizeof(T));
     d.dt = T(g.dt);
     d.inv_dx = T(1.0 / g.dx);
     for (int f = 0; f < NFIELD; ++f) d.f[f] = reinterpret_cast<T *>(ws + p->L.field[f]);
@@ -227,7 +253,7 @@ void bind(Dev<T> &d, el_plan_ *p) {
     d.P = g.npml;
     const int n[3] = {g.nx, g.ny, g.nz};
     for (int a = 0; a < 3; ++a) d.hi[a] = n[a] - 1 - g.npml;
-    d.W = g.npml > 0 ? 2 * (g.npml + 1) : 0;
+    d.W = g.npml > 0 ? 2 * (g.npml + 7) : 0;
     for (int a = 0; a < 3; ++a) {
         for (int h = 0; h < 2; ++h) {
             d.pa[a][h] = g.npml > 0 ? reinterpret_cast<T *>(ws + p->L.pa[a][h]) : nullptr;
@@ -266,7 +292,9 @@ el_status upload_receivers(el_plan_ *p, const double *rec, hipStream_t s) {
     const el_grid &g = p->g;
     const int L = p->nrec;
     const int n[3] = {g.nx, g.ny, g.nz};
+    const Vol v = make_vol(g.nx, g.ny, g.nz);
     std::vector<long long> idx(8 * (size_t)L);
+    std::vector<int> cidx(3 * 8 * (size_t)L);
     std::vector<double> w(8 * (size_t)L);
     for (int l = 0; l < L; ++l) {
         int b[3];
@@ -280,7 +308,10 @@ el_status upload_receivers(el_plan_ *p, const double *rec, hipStream_t s) {
         }
         for (int c = 0; c < 8; ++c) {
             const int ox = c & 1, oy = (c >> 1) & 1, oz = (c >> 2) & 1;
-            idx[8 * l + c] = (b[0] + ox) + (long long)g.nx * ((b[1] + oy) + (long long)g.ny * (b[2] + oz));
+            idx[8 * l + c] = v.origin + (long long)(b[2] + oz) * v.plane + (long long)(b[1] + oy) * v.px + (b[0] + ox);
+            cidx[3 * (8 * l + c) + 0] = b[0] + ox;
+            cidx[3 * (8 * l + c) + 1] = b[1] + oy;
+            cidx[3 * (8 * l + c) + 2] = b[2] + oz;
             w[8 * l + c] = (ox ? f[0] : 1 - f[0]) * (oy ? f[1] : 1 - f[1]) * (oz ? f[2] : 1 - f[2]);
         }
     }
@@ -289,12 +320,13 @@ el_status upload_receivers(el_plan_ *p, const double *rec, hipStream_t s) {
     for (size_t e = 0; e < order.size(); ++e) order[e] = (int)e;
     std::sort(order.begin(), order.end(), [&](int x, int y) { return idx[x] != idx[y] ? idx[x] < idx[y] : x < y; });
     std::vector<long long> pt;
-    std::vector<int> row, erec;
+    std::vector<int> ptc, row, erec;
     std::vector<double> ew;
     for (size_t e = 0; e < order.size(); ++e) {
         const int o = order[e];
         if (pt.empty() || pt.back() != idx[o]) {
             pt.push_back(idx[o]);
+            for (int a = 0; a < 3; ++a) ptc.push_back(cidx[3 * o + a]);
             row.push_back((int)e);
         }
         erec.push_back(o / 8);
@@ -308,6 +340,7 @@ el_status upload_receivers(el_plan_ *p, const double *rec, hipStream_t s) {
     r.w = reinterpret_cast<double *>(ws + p->L.rec_w);
     r.npts = (int)pt.size();
     r.pt = reinterpret_cast<long long *>(ws + p->L.csr_pt);
+    r.ptc = reinterpret_cast<int *>(ws + p->L.csr_ptc);
     r.row = reinterpret_cast<int *>(ws + p->L.csr_row);
     r.ent_rec = reinterpret_cast<int *>(ws + p->L.csr_rec);
     r.ent_w = reinterpret_cast<double *>(ws + p->L.csr_w);
@@ -315,6 +348,7 @@ el_status upload_receivers(el_plan_ *p, const double *rec, hipStream_t s) {
         HIP_TRY(hipMemcpyAsync((void *)r.idx, idx.data(), idx.size() * 8, hipMemcpyHostToDevice, s), "copy receivers");
         HIP_TRY(hipMemcpyAsync((void *)r.w, w.data(), w.size() * 8, hipMemcpyHostToDevice, s), "copy receivers");
         HIP_TRY(hipMemcpyAsync((void *)r.pt, pt.data(), pt.size() * 8, hipMemcpyHostToDevice, s), "copy receivers");
+        HIP_TRY(hipMemcpyAsync((void *)r.ptc, ptc.data(), ptc.size() * 4, hipMemcpyHostToDevice, s), "copy receivers");
         HIP_TRY(hipMemcpyAsync((void *)r.row, row.data(), row.size() * 4, hipMemcpyHostToDevice, s), "copy receivers");
         HIP_TRY(hipMemcpyAsync((void *)r.ent_rec, erec.data(), erec.size() * 4, hipMemcpyHostToDevice, s),
                 "copy receivers");
@@ -553,7 +587,16 @@ el_status el_plan_field(el_plan p, int32_t id, void **ptr, size_t *count) {
     if (id < 0 || id >= NFIELD) return fail(EL_EINVAL, "field id %d outside 0..8", id);
     if (!ptr || !count) return fail(EL_EINVAL, "ptr or count is NULL");
     *ptr = p->ws + p->L.field[id];
-    *count = (size_t)p->N;
+    *count = (size_t)make_vol(p->g.nx, p->g.ny, p->g.nz).total;
+    return EL_OK;
+}
+
+el_status el_plan_layout(el_plan p, int64_t *row_pitch, int64_t *plane_pitch, int64_t *origin) {
+    if (!p) return fail(EL_EINVAL, "plan is NULL");
+    const Vol v = make_vol(p->g.nx, p->g.ny, p->g.nz);
+    if (row_pitch) *row_pitch = v.px;
+    if (plane_pitch) *plane_pitch = v.plane;
+    if (origin) *origin = v.origin;
     return EL_OK;
 }
 

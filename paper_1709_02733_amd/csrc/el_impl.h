@@ -1,5 +1,18 @@
 // Internal declarations of the elastic operator library (device parameter
 // block, workspace layout, kernel launchers).  Not part of the public ABI.
+//
+// Volume layout.  Every wavefield and material array is stored padded:
+// row pitch px >= nx + 2 (a multiple of 32 elements), py = ny + 2 rows per
+// plane, and nz + 4 planes of which the first and last two are guards.
+// Cell (i, j, k) sits at element (k + 2) * px * py + j * px + i.  The
+// padding of a wavefield is zero and is never written, so a stencil tap that
+// leaves the grid (by at most two cells along one axis) reads zero -- the
+// zero extension of the fields -- without a bounds check: a tap at i = -1 or
+// -2 lands in the padding columns at the end of the previous row, a tap at
+// j = -1, -2 in the padding rows at the end of the previous plane, and taps
+// beyond the upper faces in the padding of the same row or plane.  Material
+// maps hold, in their +x, +y, +z padding, the value of the nearest cell, so
+// the staggered averages at the last index replicate it.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -14,17 +27,30 @@ namespace el {
 // Wavefield array ids (same order as el_plan_field).
 enum Field { U1 = 0, U2, U3, S11, S22, S33, S23, S13, S12, NFIELD };
 
+// Padded volume geometry (elements).
+struct Vol {
+    int nx, ny, nz;
+    int px, py;              // row pitch, rows per plane
+    long long plane;         // px * py
+    long long total;         // plane * (nz + 4)
+    long long origin;        // element of cell (0,0,0): 2 * plane
+};
+Vol make_vol(int nx, int ny, int nz);
+
 // Everything a stencil kernel needs, passed by value.
 template <typename T>
 struct Dev {
     int nx, ny, nz;
-    long long nxy;           // nx * ny
+    unsigned sy, sz;         // byte strides of +y and +z (the +x stride is sizeof(T))
+    unsigned origin;         // byte offset of cell (0,0,0)
+    int px;                  // row pitch (elements)
+    long long plane;         // plane size (elements)
     T dt, inv_dx;
-    T *f[NFIELD];            // u1, u2, u3, s11, s22, s33, s23, s13, s12
-    const T *lam, *mu, *rho, *alpha;   // cell maps
+    T *f[NFIELD];            // u1, u2, u3, s11, s22, s33, s23, s13, s12 (padded)
+    const T *lam, *mu, *rho, *alpha;   // cell maps (padded, edge-replicated)
     int P;                   // C-PML cells per face, 0 = none
     int hi[3];               // first index of the high boundary slab per axis: n - 1 - P
-    int W;                   // slab planes per axis: 2 (P + 1)
+    int W;                   // slab planes per axis: 2 (P + 7)
     const T *pa[3][2];       // PML a per axis, [0] integer / [1] half positions
     const T *pb[3][2];       // PML b
     T *mem[3][6];            // boundary-slab memory variables of axis j:
@@ -32,9 +58,43 @@ struct Dev {
                              //   mem[j][3 + i] = psi^{ij} (sigma^{ij} point)
 };
 
+// Boundary-slab storage of the C-PML memory variables.  Along each axis the variables live on
+// two extended ranges of planes: the low range covers coordinates -2 .. P+4 and the high
+// range hi-4 .. n+1 (hi = n-1-P), stored at slab coordinates 0 .. P+6 and P+7 .. 2P+13, so
+// W = 2 (P + 7) planes in all.  Cells of the layer (c <= P or c >= hi) own their value; the
+// extra planes let a 4-tap difference centred on any cell within two planes of a layer read
+// its taps without tests, and hold zeros (the adjoint keeps its memory variables multiplied
+// by the layer coefficient a, which vanishes outside the layer).  When both ranges cover a
+// layer cell (fewer than ten planes between the layers) the cell writes both copies.
+__host__ __device__ inline int slab_lo(int c) { return c + 2; }
+__host__ __device__ inline int slab_hi(int c, int P, int hi) { return c - (hi - 4) + P + 7; }
+// primary slab coordinate of a layer cell, -1 outside the layer
+__host__ __device__ inline int slab_own(int c, int P, int hi) {
+    return c <= P ? slab_lo(c) : (c >= hi ? slab_hi(c, P, hi) : -1);
+}
+// second copy of a layer cell covered by both ranges, -1 otherwise
+__host__ __device__ inline int slab_twin(int c, int P, int hi) {
+    return (c <= P && c >= hi - 4) ? slab_hi(c, P, hi) : ((c >= hi && c <= P + 4) ? slab_lo(c) : -1);
+}
+// slab coordinate of a cell whose 4-tap stencil along the axis reaches a layer, -1 otherwise
+__host__ __device__ inline int slab_near(int c, int P, int hi) {
+    return c <= P + 2 ? slab_lo(c) : (c >= hi - 2 ? slab_hi(c, P, hi) : -1);
+}
+template <typename T>
+__device__ inline unsigned slab_byte(const Dev<T> &d, int axis, int s, int i, int j, int k) {
+    const unsigned e = axis == 0 ? ((unsigned)k * d.ny + j) * d.W + s
+                                 : (axis == 1 ? ((unsigned)k * d.W + s) * d.nx + i : ((unsigned)s * d.ny + j) * d.nx + i);
+    return e * (unsigned)sizeof(T);
+}
+// byte stride between neighbouring slab coordinates of an axis
+template <typename T>
+__device__ inline unsigned slab_stride(const Dev<T> &d, int axis) {
+    return (unsigned)sizeof(T) * (axis == 0 ? 1u : (axis == 1 ? (unsigned)d.nx : (unsigned)d.nx * d.ny));
+}
+
 // Column tiles of the stencil passes: kTileX x kTileY cells in x-y, a chunk of zc planes in z.
 constexpr int kTileX = 64;
-constexpr int kTileY = 8;
+constexpr int kTileY = 4;
 struct Tiles {
     int ntx, nty, nzc, zc;   // tiles along x and y, z chunks, planes per chunk
     int ntiles;              // ntx * nty * nzc
@@ -42,14 +102,15 @@ struct Tiles {
 };
 Tiles make_tiles(int nx, int ny, int nz);
 
-// Receiver tables.
+// Receiver tables (cell offsets are padded element indices).
 struct Rec {
     int nrec;
-    const long long *idx;    // [L][8] corner cell indices
+    const long long *idx;    // [L][8] corner elements
     const double *w;         // [L][8] trilinear weights
     // grid-point-major transpose for the deterministic scatter
     int npts;
-    const long long *pt;     // [npts] touched cells
+    const long long *pt;     // [npts] touched elements
+    const int *ptc;          // [npts][3] their i, j, k
     const int *row;          // [npts + 1] offsets into ent_rec / ent_w
     const int *ent_rec;      // receiver of each entry
     const double *ent_w;     // weight of each entry
@@ -61,7 +122,7 @@ struct Layout {
     size_t map[4];           // lam, mu, rho, alpha
     size_t mem[3][6];
     size_t pa[3][2], pb[3][2];
-    size_t rec_idx, rec_w, csr_pt, csr_row, csr_rec, csr_w;
+    size_t rec_idx, rec_w, csr_pt, csr_ptc, csr_row, csr_rec, csr_w;
     size_t stats;            // media statistics (16 doubles)
     size_t partial;          // reduction partials
     size_t total;

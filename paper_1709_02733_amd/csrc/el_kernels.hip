@@ -11,38 +11,40 @@ namespace el {
 
 // ------------------------------------------------------------------ helpers
 
-// Position of coordinate c in the boundary slab of an axis, -1 outside it.
-__device__ __forceinline__ int slab_pos(int c, int P, int hi) {
-    if (c <= P) return c;
-    if (c >= hi) return c - hi + P + 1;
-    return -1;
-}
-
-template <typename T>
-__device__ __forceinline__ long long slab_idx(const Dev<T> &d, int axis, int s, int i, int j, int k) {
-    if (axis == 0) return ((long long)k * d.ny + j) * d.W + s;
-    if (axis == 1) return ((long long)k * d.W + s) * d.nx + i;
-    return ((long long)s * d.ny + j) * d.nx + i;
-}
-
 // ---------------------------------------------------------------- set-up
 
+// Copy the cell maps into the padded layout; the +x, +y, +z padding receives the value of the
+// nearest cell (coordinates clamped independently), the rest of the padding zero.
 template <typename T>
 __global__ void k_convert_maps(Dev<T> d, const float *lam, const float *mu, const float *rho, const float *alpha,
-                               long long n) {
-    for (long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x; p < n; p += (long long)gridDim.x * blockDim.x) {
-        const_cast<T *>(d.lam)[p] = T(lam[p]);
-        const_cast<T *>(d.mu)[p] = T(mu[p]);
-        const_cast<T *>(d.rho)[p] = T(rho[p]);
-        const_cast<T *>(d.alpha)[p] = T(alpha[p]);
+                               long long total) {
+    const long long plane = d.plane;
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
+         e += (long long)gridDim.x * blockDim.x) {
+        const long long zp = e / plane;
+        const long long rem = e - zp * plane;
+        const int y = (int)(rem / d.px), x = (int)(rem - (long long)y * d.px);
+        const int z = (int)zp - 2;
+        T vl = T(0), vm = T(0), vr = T(0), va = T(0);
+        if (z >= 0 && z <= d.nz && y <= d.ny && x <= d.nx) {
+            const long long src = min(x, d.nx - 1) + (long long)d.nx * (min(y, d.ny - 1) + (long long)d.ny * min(z, d.nz - 1));
+            vl = T(lam[src]);
+            vm = T(mu[src]);
+            vr = T(rho[src]);
+            va = T(alpha[src]);
+        }
+        const_cast<T *>(d.lam)[e] = vl;
+        const_cast<T *>(d.mu)[e] = vm;
+        const_cast<T *>(d.rho)[e] = vr;
+        const_cast<T *>(d.alpha)[e] = va;
     }
 }
 
 template <typename T>
 hipError_t launch_convert_maps(const Dev<T> &d, const float *lam, const float *mu, const float *rho,
                                const float *alpha, hipStream_t s) {
-    const long long n = d.nxy * d.nz;
-    hipLaunchKernelGGL(k_convert_maps<T>, dim3(2048), dim3(256), 0, s, d, lam, mu, rho, alpha, n);
+    const long long total = d.plane * (d.nz + 4);
+    hipLaunchKernelGGL(k_convert_maps<T>, dim3(4096), dim3(256), 0, s, d, lam, mu, rho, alpha, total);
     return hipGetLastError();
 }
 
@@ -117,16 +119,28 @@ __global__ void k_fill(T *p, long long n) {
 
 template <typename T>
 hipError_t launch_zero_state(const Dev<T> &d, hipStream_t s) {
-    const long long n = d.nxy * d.nz;
+    const long long n = d.plane * (d.nz + 4);
     for (int f = 0; f < NFIELD; ++f) {
         hipLaunchKernelGGL(k_fill<T>, dim3(2048), dim3(256), 0, s, d.f[f], n);
     }
     if (d.P > 0) {
-        const long long ns[3] = {(long long)d.W * d.ny * d.nz, (long long)d.nx * d.W * d.nz, d.nxy * d.W};
+        const long long ns[3] = {(long long)d.W * d.ny * d.nz, (long long)d.nx * d.W * d.nz,
+                                 (long long)d.nx * d.ny * d.W};
         for (int a = 0; a < 3; ++a)
             for (int q = 0; q < 6; ++q) hipLaunchKernelGGL(k_fill<T>, dim3(512), dim3(256), 0, s, d.mem[a][q], ns[a]);
     }
     return hipGetLastError();
+}
+
+// Padded element of cell number q (x fastest).
+template <typename T>
+__device__ __forceinline__ long long padded(const Dev<T> &d, long long q) {
+    const long long nxy = (long long)d.nx * d.ny;
+    const long long k = q / nxy;
+    const long long r = q - k * nxy;
+    const long long j = r / d.nx;
+    const long long i = r - j * d.nx;
+    return (k + 2) * d.plane + j * d.px + i;
 }
 
 // tau': s11 = s22 = s33 = -p0/3 (Sec. 3, eq. initialp0); other fields were zeroed.
@@ -134,15 +148,16 @@ template <typename T>
 __global__ void k_inject(Dev<T> d, const T *p0, long long n) {
     for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < n; q += (long long)gridDim.x * blockDim.x) {
         const T v = -p0[q] / T(3);
-        d.f[S11][q] = v;
-        d.f[S22][q] = v;
-        d.f[S33][q] = v;
+        const long long e = padded(d, q);
+        d.f[S11][e] = v;
+        d.f[S22][e] = v;
+        d.f[S33][e] = v;
     }
 }
 
 template <typename T>
 hipError_t launch_inject(const Dev<T> &d, const T *p0, hipStream_t s) {
-    hipLaunchKernelGGL(k_inject<T>, dim3(2048), dim3(256), 0, s, d, p0, d.nxy * d.nz);
+    hipLaunchKernelGGL(k_inject<T>, dim3(4096), dim3(256), 0, s, d, p0, (long long)d.nx * d.ny * d.nz);
     return hipGetLastError();
 }
 
@@ -178,8 +193,8 @@ hipError_t launch_gather(const Dev<T> &d, const Rec &r, double *row, hipStream_t
 
 // s_kk += Theta^T y_m at the touched cells (entries summed in a fixed order).  With the
 // adjoint stress kept as w = C s this adds (3 lambda + 2 mu) delta to w11, w22, w33, and the
-// normal adjoint memory variables, which hold b psi~ + dt w for the coming step, receive
-// dt times the same increment.
+// normal adjoint memory variables, which hold a (b psi~ + dt w) for the coming step, receive
+// a dt times the same increment.
 template <typename T>
 __global__ void k_scatter(Dev<T> d, Rec r, const double *y) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -192,12 +207,17 @@ __global__ void k_scatter(Dev<T> d, Rec r, const double *y) {
     d.f[S22][q] += dw;
     d.f[S33][q] += dw;
     if (d.P > 0) {
-        const int i = (int)(q % d.nx), j = (int)((q / d.nx) % d.ny), k = (int)(q / d.nxy);
-        const int crd[3] = {i, j, k};
+        // premultiplied normal memory variables g = a psi~^{kk} receive a dt delta-w
+        const int crd[3] = {r.ptc[3 * t], r.ptc[3 * t + 1], r.ptc[3 * t + 2]};
         for (int a = 0; a < 3; ++a) {
-            const int s = slab_pos(crd[a], d.P, d.hi[a]);
+            const int s = slab_own(crd[a], d.P, d.hi[a]);
             if (s < 0) continue;
-            d.mem[a][3 + a][slab_idx(d, a, s, i, j, k)] += d.dt * dw;
+            const T inc = d.pa[a][0][crd[a]] * d.dt * dw;
+            T *g = d.mem[a][3 + a];
+            const unsigned b = slab_byte(d, a, s, crd[0], crd[1], crd[2]) / sizeof(T);
+            g[b] += inc;
+            const int tw = slab_twin(crd[a], d.P, d.hi[a]);
+            if (tw >= 0) g[slab_byte(d, a, tw, crd[0], crd[1], crd[2]) / sizeof(T)] += inc;
         }
     }
 }
@@ -212,12 +232,14 @@ hipError_t launch_scatter(const Dev<T> &d, const Rec &r, const double *y, hipStr
 // p_adj = tau'^T v_0 = -(s11 + s22 + s33) / 3, with tr s = (w11 + w22 + w33) / (3 lambda + 2 mu).
 template <typename T>
 __global__ void k_extract(Dev<T> d, T *out, long long n) {
-    for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < n; q += (long long)gridDim.x * blockDim.x)
-        out[q] = -(d.f[S11][q] + d.f[S22][q] + d.f[S33][q]) / (T(3) * (T(3) * d.lam[q] + T(2) * d.mu[q]));
+    for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < n; q += (long long)gridDim.x * blockDim.x) {
+        const long long e = padded(d, q);
+        out[q] = -(d.f[S11][e] + d.f[S22][e] + d.f[S33][e]) / (T(3) * (T(3) * d.lam[e] + T(2) * d.mu[e]));
+    }
 }
 template <typename T>
 hipError_t launch_extract(const Dev<T> &d, T *p, hipStream_t s) {
-    hipLaunchKernelGGL(k_extract<T>, dim3(2048), dim3(256), 0, s, d, p, d.nxy * d.nz);
+    hipLaunchKernelGGL(k_extract<T>, dim3(4096), dim3(256), 0, s, d, p, (long long)d.nx * d.ny * d.nz);
     return hipGetLastError();
 }
 

@@ -38,7 +38,7 @@ class Grid(ctypes.Structure):
 _lib = None
 EXPORTS = ("el_version", "el_status_string", "el_last_error", "el_grid_check", "el_plan_bytes",
            "el_plan_create", "el_plan_destroy", "el_forward", "el_adjoint", "el_dot_f64",
-           "el_plan_field", "el_plan_sizes", "el_plan_timing", "el_plan_kernel_time")
+           "el_plan_field", "el_plan_layout", "el_plan_sizes", "el_plan_timing", "el_plan_kernel_time")
 KERNELS = ("velocity", "stress", "adj_velocity", "adj_stress", "gather", "scatter")
 
 
@@ -71,6 +71,9 @@ def lib():
         L.el_dot_f64.argtypes = [vp, i32, vp, vp, vp, vp]
         L.el_plan_field.restype = st
         L.el_plan_field.argtypes = [vp, i32, ctypes.POINTER(vp), ctypes.POINTER(ctypes.c_size_t)]
+        L.el_plan_layout.restype = st
+        L.el_plan_layout.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
+                                     ctypes.POINTER(ctypes.c_int64)]
         L.el_plan_sizes.restype = st
         L.el_plan_sizes.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(i32), ctypes.POINTER(i32)]
         L.el_plan_timing.restype = st
@@ -231,6 +234,10 @@ class Plan:
         ptr = ctypes.c_void_p(None)
         cnt = ctypes.c_size_t(0)
         _check(lib().el_plan_field(self._h, fid, ctypes.byref(ptr), ctypes.byref(cnt)))
+        px, pl, org = ctypes.c_int64(0), ctypes.c_int64(0), ctypes.c_int64(0)
+        _check(lib().el_plan_layout(self._h, ctypes.byref(px), ctypes.byref(pl), ctypes.byref(org)))
         off = ptr.value - self.workspace.data_ptr()
         es = 8 if self.precision == "f64" else 4
-        return self.workspace[off:off + cnt.value * es].view(self.dtype).view(self.shape)
+        flat = self.workspace[off:off + cnt.value * es].view(self.dtype)
+        nz, ny, nx = self.shape
+        return flat.as_strided((nz, ny, nx), (pl.value, px.value, 1), flat.storage_offset() + org.value)

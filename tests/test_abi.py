@@ -76,4 +76,15 @@ def test_plan_bytes_scales_with_precision_and_grid():
     assert el.plan_bytes(_g(npml=0), 5) < b32
     big = el.make_grid(384, 384, 384, 1e-4, 1e-8, 2500, 16)
     nb = el.plan_bytes(big, 1024)
-    assert 13 * 384 ** 3 * 4 < nb < 16 * 384 ** 3 * 4
+    # 13 padded volumes (rows of 416 >= 384 + 2 elements, 386 rows, 388 planes) plus boundary slabs
+    padded = 416 * 386 * 388
+    assert 13 * padded * 4 < nb < 1.2 * 13 * padded * 4
+
+
+def test_grid_check_rejects_arrays_beyond_32bit_offsets():
+    el.grid_check(el.make_grid(1000, 1000, 900, 1e-4, 1e-8, 10, 16))            # ~3.7 GiB per array: accepted
+    with pytest.raises(el.ElError) as ei:
+        el.grid_check(el.make_grid(1100, 1100, 1000, 1e-4, 1e-8, 10, 16))       # > 4 GiB per array
+    assert ei.value.status == el.EL_EINVAL
+    with pytest.raises(el.ElError):
+        el.grid_check(el.make_grid(700, 700, 700, 1e-4, 1e-8, 10, 16, precision="f64"))

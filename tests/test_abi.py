@@ -87,4 +87,4 @@ def test_grid_check_rejects_arrays_beyond_32bit_offsets():
         el.grid_check(el.make_grid(1100, 1100, 1000, 1e-4, 1e-8, 10, 16))       # > 4 GiB per array
     assert ei.value.status == el.EL_EINVAL
     with pytest.raises(el.ElError):
-        el.grid_check(el.make_grid(700, 700, 700, 1e-4, 1e-8, 10, 16, precision="f64"))
+        el.grid_check(el.make_grid(820, 820, 820, 1e-4, 1e-8, 10, 16, precision="f64"))   # 4.5 GiB in double

@@ -59,6 +59,7 @@ typedef int32_t el_status;
 #define EL_ERANGE    -3   /* a receiver outside [0, n-1]*dx on some axis                    */
 #define EL_ENOMEM    -4   /* workspace smaller than el_plan_bytes() says                    */
 #define EL_EDEVICE   -5   /* a HIP runtime call failed                                      */
+#define EL_EBUSY     -6   /* every executor slot is running an operation                    */
 
 #define EL_F32 0          /* fields, stencils, p0 and p_adj in float  */
 #define EL_F64 1          /* fields, stencils, p0 and p_adj in double */
@@ -195,6 +196,43 @@ el_status el_plan_sizes(el_plan plan, int64_t *ncells, int32_t *nrec, int32_t *n
  */
 el_status el_plan_timing(el_plan plan, int32_t enable);
 el_status el_plan_kernel_time(el_plan plan, int32_t kind, int64_t *launches, double *total_ms);
+
+/*
+ * Executor: many operations in flight at once (serving).
+ *
+ * An executor owns `max_slots` slots, each with its own HIP stream (default
+ * priority).  el_exec_start enqueues a whole operation of a plan on a free
+ * slot and returns at once: the initial state, then the time loop as replays
+ * of a captured graph of `chunk_steps` steps (a device step counter selects
+ * the trace row, so one graph serves every chunk), then the extraction of the
+ * adjoint.  Operations on different slots overlap on the device.  Results are
+ * identical to el_forward / el_adjoint on the same plan.  The operation is
+ * ordered after the plan's previous operation; the plan must not be used
+ * again, nor its buffers released, before el_exec_poll reports completion.
+ * The buffers (plan workspace, in, out) are the caller's, as for el_forward.
+ */
+#define EL_OP_FORWARD 0   /* in: p0 (plan precision, N), out: traces (double, M x L) */
+#define EL_OP_ADJOINT 1   /* in: y (double, M x L), out: p_adj (plan precision, N)  */
+
+typedef struct el_exec_ *el_exec;
+
+/* Create an executor on the current device.  max_slots in 1..64, chunk_steps >= 1. */
+el_status el_exec_create(el_exec *out, int32_t max_slots, int32_t chunk_steps);
+
+/* Wait for every slot, then release the executor. */
+el_status el_exec_destroy(el_exec ex);
+
+/* Start `op` on a free slot; *slot receives its index.  EL_EBUSY if all slots are busy. */
+el_status el_exec_start(el_exec ex, el_plan plan, int32_t op, const void *in, void *out, int32_t *slot);
+
+/* Non-blocking: *done = 1 once the slot's operation has completed (the slot is then free). */
+el_status el_exec_poll(el_exec ex, int32_t slot, int32_t *done);
+
+/* Block until the slot's operation has completed (the slot is then free). */
+el_status el_exec_wait(el_exec ex, int32_t slot);
+
+/* Number of slots and how many are running an operation. */
+el_status el_exec_slots(el_exec ex, int32_t *total, int32_t *busy);
 
 #ifdef __cplusplus
 }

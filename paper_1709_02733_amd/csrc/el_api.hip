@@ -16,16 +16,7 @@ namespace {
 
 thread_local std::string g_err;
 
-el_status fail(el_status st, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
-el_status fail(el_status st, const char *fmt, ...) {
-    char buf[512];
-    va_list ap;
-    va_start(ap, fmt);
-    vsnprintf(buf, sizeof buf, fmt, ap);
-    va_end(ap);
-    g_err = buf;
-    return st;
-}
+#define fail el::set_error
 
 el_status hip_fail(hipError_t e, const char *what) {
     return fail(EL_EDEVICE, "%s: %s", what, hipGetErrorString(e));
@@ -47,26 +38,17 @@ const double kRecSlack = 1e-9;
 
 }  // namespace
 
-struct el_plan_ {
-    el_grid g;
-    int nrec;
-    long long N;
-    Layout L;
-    char *ws;
-    int device;
-    Dev<float> df;
-    Dev<double> dd;
-    Rec rec;
-    Tiles tiles;
-    hipEvent_t done;
-    double cmax;
-    // benchmark instrumentation: per kernel kind, event pairs and how many are in use
-    bool timing = false;
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[EL_K_COUNT];
-    size_t used[EL_K_COUNT] = {};
-};
-
 namespace el {
+
+el_status set_error(el_status st, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
 
 Vol make_vol(int nx, int ny, int nz) {
     Vol v;
@@ -112,6 +94,7 @@ bool layout(const el_grid &g, int nrec, Layout *L) {
     L->csr_rec = take(E * 4);
     L->csr_w = take(E * 8);
     L->stats = take(16 * 8);
+    L->counter = take(256);
     L->partial = take(7 * kDotBlocks * 8);
     L->total = off;
     return true;
@@ -150,6 +133,7 @@ const char *el_status_string(el_status s) {
         case EL_ERANGE: return "EL_ERANGE";
         case EL_ENOMEM: return "EL_ENOMEM";
         case EL_EDEVICE: return "EL_EDEVICE";
+        case EL_EBUSY: return "EL_EBUSY";
         default: return "EL_UNKNOWN";
     }
 }

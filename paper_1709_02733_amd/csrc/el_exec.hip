@@ -1,0 +1,245 @@
+// Executor for many operator applications in flight at once (the serving path).
+//
+// An executor owns a few slots, each with its own HIP stream.  Starting an
+// operation on a slot enqueues all of it at once: the initial state (direct
+// launches), then the time loop as replays of a captured graph of K steps,
+// then the final extraction.  The trace row of each step comes from a device
+// counter that the receiver kernel advances, so the same K-step graph is valid
+// for every chunk.  Operations on different slots run concurrently on the
+// device; the host only polls completion events, so it is free to build the
+// next plans while the GPU works.  Results are identical to el_forward /
+// el_adjoint on the same plan: the same kernels run in the same order.
+#include <string>
+
+#include "el_impl.h"
+
+namespace {
+
+struct ExecSlot {
+    bool busy = false;
+    hipStream_t stream = nullptr;
+    hipEvent_t done = nullptr;
+    el_plan plan = nullptr;
+    hipGraphExec_t graph[2] = {nullptr, nullptr};
+};
+
+}  // namespace
+
+struct el_exec_ {
+    int device = 0;
+    int chunk = 64;
+    std::vector<ExecSlot> slots;
+};
+
+using namespace el;
+
+namespace {
+
+el_status hipf(hipError_t e, const char *what) {
+    return el::set_error(EL_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define EX_TRY(expr, what)                          \
+    do {                                            \
+        hipError_t e_ = (expr);                     \
+        if (e_ != hipSuccess) return hipf(e_, what); \
+    } while (0)
+
+template <typename T>
+hipError_t launch_step(el_plan p, const Dev<T> &d, int op, void *traces, int *ctr, hipStream_t s) {
+    hipError_t e;
+    if (op == EL_OP_FORWARD) {
+        e = launch_velocity(d, p->tiles, s);
+        if (e == hipSuccess) e = launch_stress(d, p->tiles, s);
+        if (e == hipSuccess) e = launch_gather_ctr(d, p->rec, static_cast<double *>(traces), ctr, s);
+    } else {
+        e = launch_adj_velocity(d, p->tiles, s);
+        if (e == hipSuccess) e = launch_adj_stress(d, p->tiles, s);
+        if (e == hipSuccess) e = launch_scatter_ctr(d, p->rec, static_cast<const double *>(traces), ctr, s);
+    }
+    return e;
+}
+
+template <typename T>
+el_status capture(el_plan p, const Dev<T> &d, int op, int steps, void *traces, int *ctr, hipStream_t s,
+                  hipGraphExec_t *out) {
+    hipGraph_t g = nullptr;
+    EX_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "begin capture");
+    hipError_t e = hipSuccess;
+    for (int m = 0; m < steps && e == hipSuccess; ++m) e = launch_step(p, d, op, traces, ctr, s);
+    const hipError_t e2 = hipStreamEndCapture(s, &g);
+    if (e != hipSuccess || e2 != hipSuccess) {
+        if (e2 == hipSuccess && g) (void)hipGraphDestroy(g);
+        return hipf(e != hipSuccess ? e : e2, "capture of the step graph");
+    }
+    e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    EX_TRY(e, "instantiate the step graph");
+    return EL_OK;
+}
+
+template <typename T>
+el_status start_op(el_exec ex, ExecSlot &sl, el_plan p, const Dev<T> &d, int op, const void *in, void *out) {
+    const hipStream_t s = sl.stream;
+    const int M = p->g.nsteps, L = p->nrec;
+    int *ctr = reinterpret_cast<int *>(p->ws + p->L.counter);
+    void *traces = op == EL_OP_FORWARD ? out : const_cast<void *>(in);
+    EX_TRY(hipStreamWaitEvent(s, p->done, 0), "order after the plan's previous operation");
+    EX_TRY(launch_zero_state(d, s), "zero state");
+    if (op == EL_OP_FORWARD) {
+        EX_TRY(launch_inject(d, static_cast<const T *>(in), s), "inject");
+        EX_TRY(launch_gather(d, p->rec, static_cast<double *>(out), s), "gather");
+        EX_TRY(launch_set_counter(ctr, 1, s), "counter");
+    } else {
+        EX_TRY(launch_scatter(d, p->rec, static_cast<const double *>(in) + (size_t)(M - 1) * L, s), "scatter");
+        EX_TRY(launch_set_counter(ctr, M - 2, s), "counter");
+    }
+    const int nupd = M - 1;
+    const int K = nupd < ex->chunk ? nupd : ex->chunk;
+    const int nfull = K > 0 ? nupd / K : 0;
+    const int rem = nupd - nfull * K;
+    if (K > 0) {
+        el_status st = capture(p, d, op, K, traces, ctr, s, &sl.graph[0]);
+        if (st != EL_OK) return st;
+    }
+    if (rem > 0) {
+        el_status st = capture(p, d, op, rem, traces, ctr, s, &sl.graph[1]);
+        if (st != EL_OK) return st;
+    }
+    for (int c = 0; c < nfull; ++c) EX_TRY(hipGraphLaunch(sl.graph[0], s), "graph launch");
+    if (rem > 0) EX_TRY(hipGraphLaunch(sl.graph[1], s), "graph launch");
+    if (op == EL_OP_ADJOINT) EX_TRY(launch_extract(d, static_cast<T *>(out), s), "extract");
+    EX_TRY(hipEventRecord(p->done, s), "record plan completion");
+    EX_TRY(hipEventRecord(sl.done, s), "record slot completion");
+    return EL_OK;
+}
+
+void release(ExecSlot &sl) {
+    for (auto &g : sl.graph)
+        if (g) {
+            (void)hipGraphExecDestroy(g);
+            g = nullptr;
+        }
+    sl.plan = nullptr;
+    sl.busy = false;
+}
+
+el_status check_exec(el_exec ex, int slot) {
+    if (!ex) return el::set_error(EL_EINVAL, "executor is NULL");
+    if (slot < 0 || slot >= (int)ex->slots.size())
+        return el::set_error(EL_EINVAL, "slot %d outside 0..%d", slot, (int)ex->slots.size() - 1);
+    int dev = -1;
+    EX_TRY(hipGetDevice(&dev), "hipGetDevice");
+    if (dev != ex->device) return el::set_error(EL_EINVAL, "current device %d is not the executor's device %d", dev, ex->device);
+    return EL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+el_status el_exec_create(el_exec *out, int32_t max_slots, int32_t chunk_steps) {
+    if (!out) return el::set_error(EL_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (max_slots < 1 || max_slots > 64) return el::set_error(EL_EINVAL, "max_slots must be in 1..64");
+    if (chunk_steps < 1) return el::set_error(EL_EINVAL, "chunk_steps must be >= 1");
+    el_exec ex = new el_exec_();
+    ex->chunk = chunk_steps;
+    hipError_t e = hipGetDevice(&ex->device);
+    ex->slots.resize(max_slots);
+    for (auto &sl : ex->slots) {
+        if (e == hipSuccess) e = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming);
+    }
+    if (e != hipSuccess) {
+        el_exec_destroy(ex);
+        return hipf(e, "executor set-up");
+    }
+    *out = ex;
+    return EL_OK;
+}
+
+el_status el_exec_destroy(el_exec ex) {
+    if (!ex) return EL_OK;
+    for (auto &sl : ex->slots) {
+        if (sl.busy && sl.done) (void)hipEventSynchronize(sl.done);
+        release(sl);
+        if (sl.done) (void)hipEventDestroy(sl.done);
+        if (sl.stream) (void)hipStreamDestroy(sl.stream);
+    }
+    delete ex;
+    return EL_OK;
+}
+
+el_status el_exec_start(el_exec ex, el_plan plan, int32_t op, const void *in, void *out, int32_t *slot) {
+    if (!ex || !plan || !slot) return el::set_error(EL_EINVAL, "executor, plan or slot is NULL");
+    *slot = -1;
+    if (op != EL_OP_FORWARD && op != EL_OP_ADJOINT) return el::set_error(EL_EINVAL, "op must be EL_OP_FORWARD or EL_OP_ADJOINT");
+    if (!in || !out) {
+        if (!(plan->nrec == 0 && ((op == EL_OP_FORWARD && in) || (op == EL_OP_ADJOINT && out))))
+            return el::set_error(EL_EINVAL, "in or out is NULL");
+    }
+    if (plan->device != ex->device) return el::set_error(EL_EINVAL, "plan and executor are on different devices");
+    int k = -1;
+    for (int q = 0; q < (int)ex->slots.size(); ++q)
+        if (!ex->slots[q].busy) {
+            k = q;
+            break;
+        }
+    if (k < 0) return el::set_error(EL_EBUSY, "all %d executor slots are busy", (int)ex->slots.size());
+    el_status st = check_exec(ex, k);
+    if (st != EL_OK) return st;
+    ExecSlot &sl = ex->slots[k];
+    sl.plan = plan;
+    st = plan->g.precision == EL_F64 ? start_op(ex, sl, plan, plan->dd, op, in, out)
+                                     : start_op(ex, sl, plan, plan->df, op, in, out);
+    if (st != EL_OK) {
+        (void)hipStreamSynchronize(sl.stream);
+        release(sl);
+        return st;
+    }
+    sl.busy = true;
+    *slot = k;
+    return EL_OK;
+}
+
+el_status el_exec_poll(el_exec ex, int32_t slot, int32_t *done) {
+    el_status st = check_exec(ex, slot);
+    if (st != EL_OK) return st;
+    if (!done) return el::set_error(EL_EINVAL, "done is NULL");
+    ExecSlot &sl = ex->slots[slot];
+    if (!sl.busy) {
+        *done = 1;
+        return EL_OK;
+    }
+    const hipError_t e = hipEventQuery(sl.done);
+    if (e == hipErrorNotReady) {
+        *done = 0;
+        return EL_OK;
+    }
+    if (e != hipSuccess) return hipf(e, "poll");
+    release(sl);
+    *done = 1;
+    return EL_OK;
+}
+
+el_status el_exec_wait(el_exec ex, int32_t slot) {
+    el_status st = check_exec(ex, slot);
+    if (st != EL_OK) return st;
+    ExecSlot &sl = ex->slots[slot];
+    if (!sl.busy) return EL_OK;
+    EX_TRY(hipEventSynchronize(sl.done), "wait");
+    release(sl);
+    return EL_OK;
+}
+
+el_status el_exec_slots(el_exec ex, int32_t *total, int32_t *busy) {
+    if (!ex) return el::set_error(EL_EINVAL, "executor is NULL");
+    int b = 0;
+    for (auto &sl : ex->slots) b += sl.busy ? 1 : 0;
+    if (total) *total = (int32_t)ex->slots.size();
+    if (busy) *busy = b;
+    return EL_OK;
+}
+
+}  // extern "C"

@@ -19,6 +19,8 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <utility>
+#include <vector>
 
 #include "el.h"
 
@@ -36,6 +38,9 @@ struct Vol {
     long long origin;        // element of cell (0,0,0): 2 * plane
 };
 Vol make_vol(int nx, int ny, int nz);
+
+// Record the detail of a failure for el_last_error() and return the status.
+el_status set_error(el_status st, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
 
 // Everything a stencil kernel needs, passed by value.
 template <typename T>
@@ -124,6 +129,7 @@ struct Layout {
     size_t pa[3][2], pb[3][2];
     size_t rec_idx, rec_w, csr_pt, csr_ptc, csr_row, csr_rec, csr_w;
     size_t stats;            // media statistics (16 doubles)
+    size_t counter;          // device step counter of captured step graphs
     size_t partial;          // reduction partials
     size_t total;
 };
@@ -148,5 +154,30 @@ template <typename T> hipError_t launch_scatter(const Dev<T> &d, const Rec &r, c
 template <typename T> hipError_t launch_extract(const Dev<T> &d, T *p, hipStream_t s);
 template <typename T> hipError_t launch_dot(const T *a, const T *b, long long n, double *partial, double *out,
                                             hipStream_t s);
+hipError_t launch_set_counter(int *ctr, int v, hipStream_t s);
+template <typename T> hipError_t launch_gather_ctr(const Dev<T> &d, const Rec &r, double *traces, int *ctr,
+                                                   hipStream_t s);
+template <typename T> hipError_t launch_scatter_ctr(const Dev<T> &d, const Rec &r, const double *traces, int *ctr,
+                                                    hipStream_t s);
 
 }  // namespace el
+
+// Host state of a plan (the opaque el_plan of the ABI).
+struct el_plan_ {
+    el_grid g;
+    int nrec;
+    long long N;
+    el::Layout L;
+    char *ws;
+    int device;
+    el::Dev<float> df;
+    el::Dev<double> dd;
+    el::Rec rec;
+    el::Tiles tiles;
+    hipEvent_t done;
+    double cmax;
+    // benchmark instrumentation: per kernel kind, event pairs and how many are in use
+    bool timing = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[EL_K_COUNT];
+    size_t used[EL_K_COUNT] = {};
+};

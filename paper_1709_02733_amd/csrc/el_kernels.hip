@@ -196,9 +196,67 @@ hipError_t launch_gather(const Dev<T> &d, const Rec &r, double *row, hipStream_t
 // normal adjoint memory variables, which hold a (b psi~ + dt w) for the coming step, receive
 // a dt times the same increment.
 template <typename T>
+__device__ __forceinline__ void scatter_point(const Dev<T> &d, const Rec &r, const double *y, int t);
+
+template <typename T>
 __global__ void k_scatter(Dev<T> d, Rec r, const double *y) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= r.npts) return;
+    scatter_point(d, r, y, t);
+}
+
+template <typename T>
+hipError_t launch_scatter(const Dev<T> &d, const Rec &r, const double *y, hipStream_t s) {
+    if (r.npts == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_scatter<T>, dim3((r.npts + 255) / 256), dim3(256), 0, s, d, r, y);
+    return hipGetLastError();
+}
+
+// ------------------------------------------- receivers with a device step counter
+//
+// Variants used inside captured step graphs: the trace row is read from a device counter
+// that the kernel advances when it is done, so one graph of K steps can be replayed.
+// Both run as one block that loops over its work.
+
+__global__ void k_set_counter(int *ctr, int v) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *ctr = v;
+}
+
+hipError_t launch_set_counter(int *ctr, int v, hipStream_t s) {
+    hipLaunchKernelGGL(k_set_counter, dim3(1), dim3(64), 0, s, ctr, v);
+    return hipGetLastError();
+}
+
+template <typename T>
+__global__ __launch_bounds__(1024) void k_gather_ctr(Dev<T> d, Rec r, double *traces, int *ctr) {
+    const int row = *ctr;
+    double *out = traces + (size_t)row * r.nrec;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int c = lane & 7;
+    for (int l0 = 0; l0 < r.nrec; l0 += 16 * 8) {
+        const int l = l0 + wave * 8 + (lane >> 3);
+        double v = 0.0;
+        if (l < r.nrec) {
+            const long long q = r.idx[8 * l + c];
+            v = r.w[8 * l + c] * ((double)d.f[S11][q] + (double)d.f[S22][q] + (double)d.f[S33][q]);
+        }
+        v += __shfl_xor(v, 1);
+        v += __shfl_xor(v, 2);
+        v += __shfl_xor(v, 4);
+        if (l < r.nrec && c == 0) out[l] = -v;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) *ctr = row + 1;
+}
+
+template <typename T>
+hipError_t launch_gather_ctr(const Dev<T> &d, const Rec &r, double *traces, int *ctr, hipStream_t s) {
+    hipLaunchKernelGGL(k_gather_ctr<T>, dim3(1), dim3(1024), 0, s, d, r, traces, ctr);
+    return hipGetLastError();
+}
+
+template <typename T>
+__device__ __forceinline__ void scatter_point(const Dev<T> &d, const Rec &r, const double *y, int t) {
     double acc = 0.0;
     for (int e = r.row[t]; e < r.row[t + 1]; ++e) acc += r.ent_w[e] * y[r.ent_rec[e]];
     const long long q = r.pt[t];
@@ -207,15 +265,13 @@ __global__ void k_scatter(Dev<T> d, Rec r, const double *y) {
     d.f[S22][q] += dw;
     d.f[S33][q] += dw;
     if (d.P > 0) {
-        // premultiplied normal memory variables g = a psi~^{kk} receive a dt delta-w
         const int crd[3] = {r.ptc[3 * t], r.ptc[3 * t + 1], r.ptc[3 * t + 2]};
         for (int a = 0; a < 3; ++a) {
             const int s = slab_own(crd[a], d.P, d.hi[a]);
             if (s < 0) continue;
             const T inc = d.pa[a][0][crd[a]] * d.dt * dw;
             T *g = d.mem[a][3 + a];
-            const unsigned b = slab_byte(d, a, s, crd[0], crd[1], crd[2]) / sizeof(T);
-            g[b] += inc;
+            g[slab_byte(d, a, s, crd[0], crd[1], crd[2]) / sizeof(T)] += inc;
             const int tw = slab_twin(crd[a], d.P, d.hi[a]);
             if (tw >= 0) g[slab_byte(d, a, tw, crd[0], crd[1], crd[2]) / sizeof(T)] += inc;
         }
@@ -223,9 +279,17 @@ __global__ void k_scatter(Dev<T> d, Rec r, const double *y) {
 }
 
 template <typename T>
-hipError_t launch_scatter(const Dev<T> &d, const Rec &r, const double *y, hipStream_t s) {
-    if (r.npts == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_scatter<T>, dim3((r.npts + 255) / 256), dim3(256), 0, s, d, r, y);
+__global__ __launch_bounds__(1024) void k_scatter_ctr(Dev<T> d, Rec r, const double *traces, int *ctr) {
+    const int row = *ctr;
+    const double *y = traces + (size_t)row * r.nrec;
+    for (int t = threadIdx.x; t < r.npts; t += blockDim.x) scatter_point(d, r, y, t);
+    __syncthreads();
+    if (threadIdx.x == 0) *ctr = row - 1;
+}
+
+template <typename T>
+hipError_t launch_scatter_ctr(const Dev<T> &d, const Rec &r, const double *traces, int *ctr, hipStream_t s) {
+    hipLaunchKernelGGL(k_scatter_ctr<T>, dim3(1), dim3(1024), 0, s, d, r, traces, ctr);
     return hipGetLastError();
 }
 
@@ -292,6 +356,8 @@ hipError_t launch_dot(const T *a, const T *b, long long n, double *partial, doub
     template hipError_t launch_gather<T>(const Dev<T> &, const Rec &, double *, hipStream_t);                        \
     template hipError_t launch_scatter<T>(const Dev<T> &, const Rec &, const double *, hipStream_t);                 \
     template hipError_t launch_extract<T>(const Dev<T> &, T *, hipStream_t);                                         \
+    template hipError_t launch_gather_ctr<T>(const Dev<T> &, const Rec &, double *, int *, hipStream_t);             \
+    template hipError_t launch_scatter_ctr<T>(const Dev<T> &, const Rec &, const double *, int *, hipStream_t);                                         \
     template hipError_t launch_dot<T>(const T *, const T *, long long, double *, double *, hipStream_t);
 
 EL_INST(float)

@@ -16,7 +16,8 @@ import torch
 _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libel.so")
 
-EL_OK, EL_EINVAL, EL_EUNSTABLE, EL_ERANGE, EL_ENOMEM, EL_EDEVICE = 0, -1, -2, -3, -4, -5
+EL_OK, EL_EINVAL, EL_EUNSTABLE, EL_ERANGE, EL_ENOMEM, EL_EDEVICE, EL_EBUSY = 0, -1, -2, -3, -4, -5, -6
+OP_FORWARD, OP_ADJOINT = 0, 1
 EL_F32, EL_F64 = 0, 1
 FIELDS = ("u1", "u2", "u3", "s11", "s22", "s33", "s23", "s13", "s12")
 
@@ -38,7 +39,8 @@ class Grid(ctypes.Structure):
 _lib = None
 EXPORTS = ("el_version", "el_status_string", "el_last_error", "el_grid_check", "el_plan_bytes",
            "el_plan_create", "el_plan_destroy", "el_forward", "el_adjoint", "el_dot_f64",
-           "el_plan_field", "el_plan_layout", "el_plan_sizes", "el_plan_timing", "el_plan_kernel_time")
+           "el_plan_field", "el_plan_layout", "el_plan_sizes", "el_plan_timing", "el_plan_kernel_time",
+           "el_exec_create", "el_exec_destroy", "el_exec_start", "el_exec_poll", "el_exec_wait", "el_exec_slots")
 KERNELS = ("velocity", "stress", "adj_velocity", "adj_stress", "gather", "scatter")
 
 
@@ -80,6 +82,18 @@ def lib():
         L.el_plan_timing.argtypes = [vp, i32]
         L.el_plan_kernel_time.restype = st
         L.el_plan_kernel_time.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)]
+        L.el_exec_create.restype = st
+        L.el_exec_create.argtypes = [ctypes.POINTER(vp), i32, i32]
+        L.el_exec_destroy.restype = st
+        L.el_exec_destroy.argtypes = [vp]
+        L.el_exec_start.restype = st
+        L.el_exec_start.argtypes = [vp, vp, i32, vp, vp, ctypes.POINTER(i32)]
+        L.el_exec_poll.restype = st
+        L.el_exec_poll.argtypes = [vp, i32, ctypes.POINTER(i32)]
+        L.el_exec_wait.restype = st
+        L.el_exec_wait.argtypes = [vp, i32]
+        L.el_exec_slots.restype = st
+        L.el_exec_slots.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
         _lib = L
     return _lib
 
@@ -241,3 +255,57 @@ class Plan:
         flat = self.workspace[off:off + cnt.value * es].view(self.dtype)
         nz, ny, nx = self.shape
         return flat.as_strided((nz, ny, nx), (pl.value, px.value, 1), flat.storage_offset() + org.value)
+
+
+class Executor:
+    """Several operator applications in flight at once (one HIP stream per slot).
+
+    start() enqueues a whole forward or adjoint application of a plan on a free
+    slot and returns the slot; poll()/wait() report completion.  The plan and
+    the in/out tensors are kept alive here until the operation has completed.
+    """
+
+    def __init__(self, max_slots: int = 4, chunk: int = 64, device=None):
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        h = ctypes.c_void_p(None)
+        with torch.cuda.device(self.device):
+            _check(lib().el_exec_create(ctypes.byref(h), int(max_slots), int(chunk)))
+        self._h = h
+        self.max_slots = int(max_slots)
+        self._held = {}
+
+    def start(self, plan: "Plan", op: int, inp: torch.Tensor, out: torch.Tensor) -> int:
+        slot = ctypes.c_int32(-1)
+        with torch.cuda.device(self.device):
+            _check(lib().el_exec_start(self._h, plan._h, int(op), ctypes.c_void_p(inp.data_ptr()),
+                                       ctypes.c_void_p(out.data_ptr()), ctypes.byref(slot)))
+        self._held[slot.value] = (plan, inp, out)
+        return slot.value
+
+    def poll(self, slot: int) -> bool:
+        done = ctypes.c_int32(0)
+        with torch.cuda.device(self.device):
+            _check(lib().el_exec_poll(self._h, int(slot), ctypes.byref(done)))
+        if done.value:
+            self._held.pop(slot, None)
+        return bool(done.value)
+
+    def wait(self, slot: int):
+        with torch.cuda.device(self.device):
+            _check(lib().el_exec_wait(self._h, int(slot)))
+        self._held.pop(slot, None)
+
+    def slots(self):
+        t, b = ctypes.c_int32(0), ctypes.c_int32(0)
+        _check(lib().el_exec_slots(self._h, ctypes.byref(t), ctypes.byref(b)))
+        return t.value, b.value
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            with torch.cuda.device(self.device):
+                lib().el_exec_destroy(h)
+        self._h = None
+        self._held = {}
+
+    __del__ = close

@@ -1,0 +1,109 @@
+"""Serving on the GPU: requests of uneven sizes run concurrently through the executor
+(captured step graphs on per-slot streams) and every result is bitwise the same as
+the same request run alone through el_forward / el_adjoint."""
+import dataclasses
+
+import numpy as np
+import pytest
+import torch
+
+from oracle.oracle import Model
+from paper_1709_02733_amd import el
+from paper_1709_02733_amd import scenarios as S
+from paper_1709_02733_amd import serving as SV
+from tests.gpu_util import banner, need_gpu, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(autouse=True)
+def _gpu(request):
+    need_gpu()
+    banner(request.node.nodeid)
+    yield
+    torch.cuda.synchronize()
+
+
+@pytest.fixture(scope="module")
+def small():
+    wl = SV.Workloads(sizes=(40, 48, 56), keep_outputs=True)
+    reqs = []
+    rng = np.random.default_rng(0)
+    for k in range(9):
+        n = (40, 48, 56)[k % 3]
+        reqs.append(SV.Request(rid=k, op=k % 2, n=n, nsteps=int(rng.integers(40, 90)), nrec=int(rng.integers(20, 80)),
+                               seed=1000 + k, arrival=0.002 * k))
+    return wl, reqs
+
+
+def _alone(wl, r):
+    plan = wl.plan(r)
+    inp, out = wl.io(r)
+    if r.op == 0:
+        plan.forward(inp, out=out)
+    else:
+        plan.adjoint(inp, out=out)
+    torch.cuda.synchronize()
+    return out
+
+
+def test_batched_results_equal_alone(small):
+    wl, reqs = small
+    ex = el.Executor(max_slots=3, chunk=16)
+    batched = SV.run_batched(SV.clone_requests(reqs), wl, ex, budget_bytes=1e12)
+    assert all(r.done is not None for r in batched)
+    for r in batched:
+        alone = _alone(wl, r)
+        assert torch.equal(r.output, alone), (r.rid, r.op, r.n, r.nsteps)
+    ex.close()
+
+
+def test_plain_and_batched_agree_and_match_oracle(small):
+    wl, reqs = small
+    ex = el.Executor(max_slots=2, chunk=7)
+    a = SV.run_plain(SV.clone_requests(reqs), wl)
+    b = SV.run_batched(SV.clone_requests(reqs), wl, ex, budget_bytes=1e12)
+    for ra, rb in zip(a, b):
+        assert torch.equal(ra.output, rb.output)
+    # one forward and one adjoint request against the FP64 oracle
+    for r in (b[0], b[1]):
+        sc = wl.media[r.n]["sc"]
+        m = Model(r.n, r.n, r.n, sc.dx, sc.dt, r.nsteps, 16, sc.lam, sc.mu, sc.rho, sc.alpha, wl.receivers(r))
+        inp, _ = wl.io(r)
+        ref = m.forward(inp.double().cpu().numpy()) if r.op == 0 else m.adjoint(inp.cpu().numpy())
+        e = rel_l2(r.output.cpu().numpy(), ref)
+        banner(f"request {r.rid} op {r.op} n {r.n}: rel L2 vs oracle {e:.2e}")
+        assert e <= 1e-4
+    ex.close()
+
+
+def test_budget_limits_concurrency(small):
+    wl, reqs = small
+    ex = el.Executor(max_slots=3, chunk=16)
+    reqs = SV.clone_requests(reqs)
+    big = max(wl.footprint(r) for r in reqs)
+    budget = 2.2 * big
+    trace = []
+    out = SV.run_batched(reqs, wl, ex, budget_bytes=budget, trace=trace)
+    assert all(r.done is not None for r in out)
+    assert all(used <= budget for _, used, _ in trace)
+    assert max(a for _, _, a in trace) <= 3
+    ex.close()
+
+
+def test_executor_rejects_when_full(small):
+    wl, reqs = small
+    ex = el.Executor(max_slots=1, chunk=8)
+    r0, r1 = reqs[0], reqs[2]
+    p0, p1 = wl.plan(r0), wl.plan(r1)
+    i0, o0 = wl.io(r0)
+    i1, o1 = wl.io(r1)
+    s0 = ex.start(p0, r0.op, i0, o0)
+    with pytest.raises(el.ElError) as ei:
+        ex.start(p1, r1.op, i1, o1)
+    assert ei.value.status == el.EL_EBUSY
+    ex.wait(s0)
+    s1 = ex.start(p1, r1.op, i1, o1)
+    ex.wait(s1)
+    assert ex.slots() == (1, 0)
+    ex.close()

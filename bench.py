@@ -105,6 +105,9 @@ def main():
     ap.add_argument("--nsteps", type=int, default=0, help="override the trace length M (diagnostics only)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-sample-steps", type=int, default=3)
+    ap.add_argument("--no-serving", action="store_true", help="skip the plain vs batched serving comparison")
+    ap.add_argument("--serving-rates", type=float, nargs="+", default=[2.0, 10.0])
+    ap.add_argument("--serving-count", type=int, default=16)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy a 256 MiB float buffer three times (reference kernel for HBM byte counters)")
     args = ap.parse_args()
@@ -188,6 +191,21 @@ def main():
                + bytemodel.step_bytes("adj", sc.nx, sc.ny, sc.nz, sc.npml, sc.nrec)) * (sc.nsteps - 1)
     whole_gbs = step_gb * args.steps / (total_ms / 1e3) / 1e9
 
+    serving = None
+    if not args.no_serving:
+        from paper_1709_02733_amd import serving as SV
+        del plan, p0, traces, padj
+        torch.cuda.empty_cache()
+        res = SV.serve_benchmark(rates=args.serving_rates, count=args.serving_count, log=log)
+        serving = {"requests_per_rate": args.serving_count,
+                   "mix": "96^3/128^3/192^3/256^3 skull media, 800-1800 samples, 256-1024 receivers, "
+                          "60% forward / 40% adjoint, Poisson arrivals, 4 executor slots, 64-step graphs, "
+                          "200 GB HBM budget",
+                   "rates": [{"rate": e["rate"],
+                              "plain": {k: e["plain"][k] for k in ("gcells", "throughput_rps", "p50_s", "p99_s")},
+                              "batched": {k: e["batched"][k] for k in ("gcells", "throughput_rps", "p50_s", "p99_s")},
+                              "throughput_gain": e["throughput_gain"]} for e in res]}
+
     cpu = None
     if not args.no_cpu:
         torch.cuda.empty_cache()
@@ -216,6 +234,7 @@ def main():
         "whole_step_gbs": whole_gbs,
         "roofline": roofline,
         "kernels": {k: {"avg_us": v["avg_us"], "gbs": v["gbs"], "launches": v["launches"]} for k, v in per.items()},
+        "serving": serving,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

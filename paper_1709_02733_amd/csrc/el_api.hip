@@ -95,15 +95,15 @@ bool layout(const el_grid &g, int nrec, Layout *L) {
     L->csr_w = take(E * 8);
     L->stats = take(16 * 8);
     L->counter = take(256);
+    L->tile_order = take((size_t)8 * make_tiles(g.nx, g.ny, g.nz).per * sizeof(int));
     L->partial = take(7 * kDotBlocks * 8);
     L->total = off;
     return true;
 }
 
 // Tiles of kTileX x kTileY columns; the z extent is cut into chunks of at most 16 planes
-// (fewer on small grids, down to 4, so that about 4096 tiles exist), and the grid is
-// padded to a multiple of 8 blocks so that block b % 8 (its XCD) owns tiles
-// [x * per, (x + 1) * per).
+// (fewer on small grids, down to 4, so that about 4096 tiles exist).  The grid has
+// 8 * per blocks; tile_order() says which tile each block processes.
 Tiles make_tiles(int nx, int ny, int nz) {
     Tiles t;
     t.ntx = (nx + kTileX - 1) / kTileX;
@@ -115,8 +115,24 @@ Tiles make_tiles(int nx, int ny, int nz) {
     t.zc = (nz + t.nzc - 1) / t.nzc;
     t.nzc = (nz + t.zc - 1) / t.zc;
     t.ntiles = t.ntx * t.nty * t.nzc;
-    t.per = (t.ntiles + 7) / 8;
+    const int run = std::max(1, (t.ntiles + 511) / 512);
+    const int nruns = (t.ntiles + run - 1) / run;
+    // XCD x receives runs x, x + 8, ...; the first XCDs may hold one run more
+    const int runs_per = (nruns + 7) / 8;
+    t.per = runs_per * run;
+    t.order = nullptr;
     return t;
+}
+
+std::vector<int> tile_order(const Tiles &t) {
+    const int run = std::max(1, (t.ntiles + 511) / 512);
+    std::vector<int> order((size_t)8 * t.per, -1);
+    std::vector<int> fill(8, 0);
+    for (int r = 0, first = 0; first < t.ntiles; ++r, first += run) {
+        const int x = r % 8;
+        for (int q = first; q < std::min(first + run, t.ntiles); ++q) order[(size_t)fill[x]++ * 8 + x] = q;
+    }
+    return order;
 }
 
 }  // namespace el
@@ -475,6 +491,14 @@ el_status el_plan_create(el_plan *out, const el_grid *grid, const float *lam, co
     if (st != EL_OK) return bail(st);
     st = upload_receivers(p, rec, s);
     if (st != EL_OK) return bail(st);
+    {
+        const std::vector<int> order = tile_order(p->tiles);
+        int *dst = reinterpret_cast<int *>(p->ws + L.tile_order);
+        e = hipMemcpyAsync(dst, order.data(), order.size() * sizeof(int), hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return bail(hip_fail(e, "tile order"));
+        p->tiles.order = dst;
+    }
     e = hipStreamSynchronize(s);
     if (e != hipSuccess) return bail(hip_fail(e, "plan set-up"));
     e = hipEventRecord(p->done, s);

@@ -104,8 +104,14 @@ struct Tiles {
     int ntx, nty, nzc, zc;   // tiles along x and y, z chunks, planes per chunk
     int ntiles;              // ntx * nty * nzc
     int per;                 // tiles per XCD: the grid has 8 * per blocks
+    const int *order;        // device: tile of each block (-1 for a padding block)
 };
 Tiles make_tiles(int nx, int ny, int nz);
+// Tile of each block: tiles in z-major order are cut into runs of about ntiles / 512
+// tiles and the runs are dealt round-robin to the eight XCDs (block b runs on XCD b % 8),
+// so every XCD receives contiguous runs from all over the volume: the same share of
+// C-PML layer cells and of interior cells, with neighbouring tiles of a run in one L2.
+std::vector<int> tile_order(const Tiles &t);
 
 // Receiver tables (cell offsets are padded element indices).
 struct Rec {
@@ -130,6 +136,7 @@ struct Layout {
     size_t rec_idx, rec_w, csr_pt, csr_ptc, csr_row, csr_rec, csr_w;
     size_t stats;            // media statistics (16 doubles)
     size_t counter;          // device step counter of captured step graphs
+    size_t tile_order;       // tile of each stencil block
     size_t partial;          // reduction partials
     size_t total;
 };

@@ -33,8 +33,9 @@
 // the tiles processed next to it keep them in L1/L2.  There is no LDS and no
 // barrier.  The padded volume layout (see el_impl.h) makes every tap a plain
 // load: addresses are a 32-bit byte offset, shared by all fields, from the
-// field's base pointer.  Blocks are numbered so that each XCD (block id mod
-// 8) receives a contiguous range of tiles.
+// field's base pointer.  Each block reads its tile from an order table that
+// gives every XCD (block id mod 8) contiguous runs of tiles from all over the
+// volume, so the C-PML layers are shared evenly among the XCDs.
 #include "el_impl.h"
 
 namespace el {
@@ -86,17 +87,30 @@ __device__ __forceinline__ void add_pml_axis(const Dev<T> &d, T (&dd)[3][3], int
     }
 }
 
+// Reciprocal: the hardware v_rcp_f32 (within 1 ulp) in single precision, the correctly
+// rounded quotient in double precision.  Both give +inf for +0 and 0 for +inf.
 template <typename T>
-__device__ __forceinline__ T harmonic4(T m0, T m1, T m2, T m3) {
-    if (m0 == T(0) || m1 == T(0) || m2 == T(0) || m3 == T(0)) return T(0);
-    return T(4) / (T(1) / m0 + T(1) / m1 + T(1) / m2 + T(1) / m3);
+__device__ __forceinline__ T rcp(T x);
+template <>
+__device__ __forceinline__ float rcp<float>(float x) {
+    return __builtin_amdgcn_rcpf(x);
+}
+template <>
+__device__ __forceinline__ double rcp<double>(double x) {
+    return 1.0 / x;
 }
 
-// Logical tile of this block (XCD-aware numbering); false for padding blocks.
+// Harmonic mean of four non-negative moduli given their reciprocals (Sec. 2.2: the shear
+// modulus at an edge point); zero when any modulus is zero, whose reciprocal is +inf.
+template <typename T>
+__device__ __forceinline__ T harmonic4r(T r0, T r1, T r2, T r3) {
+    return T(4) * rcp(r0 + r1 + r2 + r3);
+}
+
+// Tile of this block from the XCD-balanced order table; false for padding blocks.
 __device__ __forceinline__ bool tile_of(const Tiles &tl, int nz, int &x0, int &y0, int &z0, int &z1) {
-    const int b = blockIdx.x;
-    const int t = (b & 7) * tl.per + (b >> 3);
-    if (t >= tl.ntiles) return false;
+    const int t = tl.order[blockIdx.x];
+    if (t < 0) return false;
     const int bx = t % tl.ntx;
     const int r = t / tl.ntx;
     const int by = r % tl.nty;
@@ -107,6 +121,11 @@ __device__ __forceinline__ bool tile_of(const Tiles &tl, int nz, int &x0, int &y
     z1 = min(z0 + tl.zc, nz);
     return true;
 }
+
+// Each plane of a column is processed as: every load of the plane's main inputs, one
+// scheduling fence (so they are in flight together: one memory round trip per plane), the
+// arithmetic and the stores.  Where the cell lies in a C-PML layer, the memory variables of
+// each layer axis are loaded as one batch ahead of their update and store.
 
 // ------------------------------------------------------------------------
 // velocity-shaped pass.  In_ca lives in field sigma^{ca} (forward) or w_(ca) (adjoint):
@@ -120,7 +139,7 @@ __global__ __launch_bounds__(NT) void k_vel(Dev<T> d, Tiles tl) {
     if (!tile_of(tl, d.nz, x0, y0, z0, z1)) return;
     const int i = x0 + (int)threadIdx.x % TX, j = y0 + (int)threadIdx.x / TX;
     if (i >= d.nx || j >= d.ny) return;
-    const T h = d.inv_dx;
+    const T h = d.inv_dx, dt = d.dt;
     const unsigned sx = sizeof(T), sy = d.sy, sz = d.sz;
     const T *s11 = d.f[S11], *s22 = d.f[S22], *s33 = d.f[S33], *s23 = d.f[S23], *s13 = d.f[S13], *s12 = d.f[S12];
     unsigned o = d.origin + (unsigned)z0 * sz + (unsigned)j * sy + (unsigned)i * sx;
@@ -138,6 +157,7 @@ __global__ __launch_bounds__(NT) void k_vel(Dev<T> d, Tiles tl) {
     T rho_k = ldb(d.rho, o), alp_k = ldb(d.alpha, o);
     const bool pml = d.P > 0;
     const int snx = pml ? slab_near(i, d.P, d.hi[0]) : -1, sny = pml ? slab_near(j, d.P, d.hi[1]) : -1;
+    const int sox = pml ? slab_own(i, d.P, d.hi[0]) : -1, soy = pml ? slab_own(j, d.P, d.hi[1]) : -1;
     for (int k = z0; k < z1; ++k, o += sz) {
 #pragma unroll
         for (int n = 0; n < 3; ++n) {
@@ -148,21 +168,43 @@ __global__ __launch_bounds__(NT) void k_vel(Dev<T> d, Tiles tl) {
         qa[3] = ldb(s13, o + sz);
         qb[3] = ldb(s23, o + sz);
         qc[3] = ldb(s33, o + 2 * sz);
+        T a11[4], a12[4], a13[4], b12[4], b22[4], b23[4];   // taps along x (a) and y (b)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            a11[q] = ldb(s11, o + (unsigned)(q - 1) * sx);   // Dp: -1 .. +2
+            a12[q] = ldb(s12, o + (unsigned)(q - 2) * sx);   // Dm: -2 .. +1
+            a13[q] = ldb(s13, o + (unsigned)(q - 2) * sx);
+            b12[q] = ldb(s12, o + (unsigned)(q - 2) * sy);
+            b22[q] = ldb(s22, o + (unsigned)(q - 1) * sy);
+            b23[q] = ldb(s23, o + (unsigned)(q - 2) * sy);
+        }
+        T uold[3], rho_n[3], alp_n[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) uold[c] = ldb(d.f[U1 + c], o);
+        rho_n[0] = ldb(d.rho, o + sx);
+        rho_n[1] = ldb(d.rho, o + sy);
+        rho_n[2] = ldb(d.rho, o + sz);
+        alp_n[0] = ldb(d.alpha, o + sx);
+        alp_n[1] = ldb(d.alpha, o + sy);
+        alp_n[2] = ldb(d.alpha, o + sz);
+        __builtin_amdgcn_sched_barrier(0);
         T dd[3][3];
-        dd[0][0] = dp_at(s11, o, sx, h);
-        dd[1][0] = dm_at(s12, o, sx, h);
-        dd[2][0] = dm_at(s13, o, sx, h);
-        dd[0][1] = dm_at(s12, o, sy, h);
-        dd[1][1] = dp_at(s22, o, sy, h);
-        dd[2][1] = dm_at(s23, o, sy, h);
+        dd[0][0] = dplus(a11[0], a11[1], a11[2], a11[3], h);
+        dd[1][0] = dminus(a12[0], a12[1], a12[2], a12[3], h);
+        dd[2][0] = dminus(a13[0], a13[1], a13[2], a13[3], h);
+        dd[0][1] = dminus(b12[0], b12[1], b12[2], b12[3], h);
+        dd[1][1] = dplus(b22[0], b22[1], b22[2], b22[3], h);
+        dd[2][1] = dminus(b23[0], b23[1], b23[2], b23[3], h);
         dd[0][2] = dminus(qa[0], qa[1], qa[2], qa[3], h);
         dd[1][2] = dminus(qb[0], qb[1], qb[2], qb[3], h);
         dd[2][2] = dplus(qc[0], qc[1], qc[2], qc[3], h);
+        const int crd[3] = {i, j, k};
+        const int slab[3] = {sox, soy, pml ? slab_own(k, d.P, d.hi[2]) : -1};
         if (ADJ) {
 #pragma unroll
             for (int c = 0; c < 3; ++c)
 #pragma unroll
-                for (int a = 0; a < 3; ++a) dd[c][a] *= d.dt;
+                for (int a = 0; a < 3; ++a) dd[c][a] *= dt;
             const int snz = pml ? slab_near(k, d.P, d.hi[2]) : -1;
             if (snx >= 0) add_pml_axis<T, true, 0>(d, dd, snx, i, j, k, h);
             if (sny >= 0) add_pml_axis<T, true, 1>(d, dd, sny, i, j, k, h);
@@ -171,52 +213,54 @@ __global__ __launch_bounds__(NT) void k_vel(Dev<T> d, Tiles tl) {
         T acc[3];
 #pragma unroll
         for (int c = 0; c < 3; ++c) acc[c] = dd[c][0] + dd[c][1] + dd[c][2];
-        const int crd[3] = {i, j, k};
-        int slab[3] = {-1, -1, -1};
-        if (pml) {
-#pragma unroll
-            for (int a = 0; a < 3; ++a) slab[a] = slab_own(crd[a], d.P, d.hi[a]);
-        }
         if (!ADJ) {
+            // phi^{ca} <- b phi^{ca} + a D_a sigma^{ca}, one batch of loads per layer axis
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
                 if (slab[a] < 0) continue;
                 const unsigned q = slab_byte(d, a, slab[a], i, j, k);
+                T m[3];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) m[c] = ldb(d.mem[a][c], q);
+                const T ca[2] = {d.pa[a][0][crd[a]], d.pa[a][1][crd[a]]};
+                const T cb[2] = {d.pb[a][0][crd[a]], d.pb[a][1][crd[a]]};
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
                     const int half = c == a;
-                    const T phi = d.pb[a][half][crd[a]] * ldb(d.mem[a][c], q) + d.pa[a][half][crd[a]] * dd[c][a];
+                    const T phi = cb[half] * m[c] + ca[half] * dd[c][a];
                     stb(d.mem[a][c], q, phi);
                     acc[c] += phi;
                 }
             }
         }
-        const T rho_z = ldb(d.rho, o + sz), alp_z = ldb(d.alpha, o + sz);
-        const T rho_n[3] = {ldb(d.rho, o + sx), ldb(d.rho, o + sy), rho_z};
-        const T alp_n[3] = {ldb(d.alpha, o + sx), ldb(d.alpha, o + sy), alp_z};
         T out[3];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             const T rho_c = T(0.5) * (rho_k + rho_n[c]);
             const T alp_c = T(0.5) * (alp_k + alp_n[c]);
-            const T old = ldb(d.f[U1 + c], o);
-            out[c] = ADJ ? (T(1) - d.dt * alp_c) * old - acc[c] / rho_c
-                         : (T(1) - d.dt * alp_c) * old + d.dt / rho_c * acc[c];
+            const T irho = rcp(rho_c);
+            out[c] = ADJ ? (T(1) - dt * alp_c) * uold[c] - acc[c] * irho
+                         : (T(1) - dt * alp_c) * uold[c] + dt * irho * acc[c];
             stb(d.f[U1 + c], o, out[c]);
         }
-        rho_k = rho_z;
-        alp_k = alp_z;
+        rho_k = rho_n[2];
+        alp_k = alp_n[2];
         if (ADJ) {
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
                 if (slab[a] < 0) continue;
-                // g = a phi~ <- b g + a dt r   (Gamma^T q with the indicator folded into a)
+                // g' = a phi~ <- b g' + a dt r   (Gamma^T q with the indicator folded into a)
                 const unsigned q = slab_byte(d, a, slab[a], i, j, k);
                 const int tw = slab_twin(crd[a], d.P, d.hi[a]);
+                T m[3];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) m[c] = ldb(d.mem[a][c], q);
+                const T ca[2] = {d.pa[a][0][crd[a]], d.pa[a][1][crd[a]]};
+                const T cb[2] = {d.pb[a][0][crd[a]], d.pb[a][1][crd[a]]};
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
                     const int half = c == a;
-                    const T g = d.pb[a][half][crd[a]] * ldb(d.mem[a][c], q) + d.pa[a][half][crd[a]] * d.dt * out[c];
+                    const T g = cb[half] * m[c] + ca[half] * dt * out[c];
                     stb(d.mem[a][c], q, g);
                     if (tw >= 0) stb(d.mem[a][c], slab_byte(d, a, tw, i, j, k), g);
                 }
@@ -235,7 +279,7 @@ __global__ __launch_bounds__(NT) void k_str(Dev<T> d, Tiles tl) {
     if (!tile_of(tl, d.nz, x0, y0, z0, z1)) return;
     const int i = x0 + (int)threadIdx.x % TX, j = y0 + (int)threadIdx.x / TX;
     if (i >= d.nx || j >= d.ny) return;
-    const T h = d.inv_dx;
+    const T h = d.inv_dx, dt = d.dt;
     const unsigned sx = sizeof(T), sy = d.sy, sz = d.sz;
     const T *u1 = d.f[U1], *u2 = d.f[U2], *u3 = d.f[U3];
     unsigned o = d.origin + (unsigned)z0 * sz + (unsigned)j * sy + (unsigned)i * sx;
@@ -250,10 +294,13 @@ __global__ __launch_bounds__(NT) void k_str(Dev<T> d, Tiles tl) {
     qc[1] = ldb(u3, o - 2 * sz);
     qc[2] = ldb(u3, o - sz);
     qc[3] = ldb(u3, o);
-    // mu at the cell and its +x, +y neighbours of the current plane (carried from the previous plane)
-    T m0 = ldb(d.mu, o), mx = ldb(d.mu, o + sx), my = ldb(d.mu, o + sy);
+    // mu at the cell and its +x, +y neighbours of the current plane, and their reciprocals
+    // (carried from the previous plane)
+    T m0 = ldb(d.mu, o);
+    T r0 = rcp(m0), rx = rcp(ldb(d.mu, o + sx)), ry = rcp(ldb(d.mu, o + sy));
     const bool pml = d.P > 0;
     const int snx = pml ? slab_near(i, d.P, d.hi[0]) : -1, sny = pml ? slab_near(j, d.P, d.hi[1]) : -1;
+    const int sox = pml ? slab_own(i, d.P, d.hi[0]) : -1, soy = pml ? slab_own(j, d.P, d.hi[1]) : -1;
     for (int k = z0; k < z1; ++k, o += sz) {
 #pragma unroll
         for (int n = 0; n < 3; ++n) {
@@ -264,70 +311,84 @@ __global__ __launch_bounds__(NT) void k_str(Dev<T> d, Tiles tl) {
         qa[3] = ldb(u1, o + 2 * sz);
         qb[3] = ldb(u2, o + 2 * sz);
         qc[3] = ldb(u3, o + sz);
+        T a1[4], a2[4], a3[4], b1[4], b2[4], b3[4];   // taps along x (a) and y (b)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            a1[q] = ldb(u1, o + (unsigned)(q - 2) * sx);   // Dm: -2 .. +1
+            a2[q] = ldb(u2, o + (unsigned)(q - 1) * sx);   // Dp: -1 .. +2
+            a3[q] = ldb(u3, o + (unsigned)(q - 1) * sx);
+            b1[q] = ldb(u1, o + (unsigned)(q - 1) * sy);
+            b2[q] = ldb(u2, o + (unsigned)(q - 2) * sy);
+            b3[q] = ldb(u3, o + (unsigned)(q - 1) * sy);
+        }
+        T sold[6];
+#pragma unroll
+        for (int c = 0; c < 6; ++c) sold[c] = ldb(d.f[S11 + c], o);
+        const T lam = ldb(d.lam, o);
+        const T mz = ldb(d.mu, o + sz), mxz = ldb(d.mu, o + sx + sz), myz = ldb(d.mu, o + sy + sz);
+        const T mxy = ldb(d.mu, o + sx + sy);
+        __builtin_amdgcn_sched_barrier(0);
         T e[3][3];   // e[c][a] = D_a In_ca
-        e[0][0] = dm_at(u1, o, sx, h);
-        e[1][0] = dp_at(u2, o, sx, h);
-        e[2][0] = dp_at(u3, o, sx, h);
-        e[0][1] = dp_at(u1, o, sy, h);
-        e[1][1] = dm_at(u2, o, sy, h);
-        e[2][1] = dp_at(u3, o, sy, h);
+        e[0][0] = dminus(a1[0], a1[1], a1[2], a1[3], h);
+        e[1][0] = dplus(a2[0], a2[1], a2[2], a2[3], h);
+        e[2][0] = dplus(a3[0], a3[1], a3[2], a3[3], h);
+        e[0][1] = dplus(b1[0], b1[1], b1[2], b1[3], h);
+        e[1][1] = dminus(b2[0], b2[1], b2[2], b2[3], h);
+        e[2][1] = dplus(b3[0], b3[1], b3[2], b3[3], h);
         e[0][2] = dplus(qa[0], qa[1], qa[2], qa[3], h);
         e[1][2] = dplus(qb[0], qb[1], qb[2], qb[3], h);
         e[2][2] = dminus(qc[0], qc[1], qc[2], qc[3], h);
+        const int crd[3] = {i, j, k};
+        const int slab[3] = {sox, soy, pml ? slab_own(k, d.P, d.hi[2]) : -1};
         if (ADJ) {
 #pragma unroll
             for (int c = 0; c < 3; ++c)
 #pragma unroll
-                for (int a = 0; a < 3; ++a) e[c][a] *= d.dt;
+                for (int a = 0; a < 3; ++a) e[c][a] *= dt;
             const int snz = pml ? slab_near(k, d.P, d.hi[2]) : -1;
             if (snx >= 0) add_pml_axis<T, false, 0>(d, e, snx, i, j, k, h);
             if (sny >= 0) add_pml_axis<T, false, 1>(d, e, sny, i, j, k, h);
             if (snz >= 0) add_pml_axis<T, false, 2>(d, e, snz, i, j, k, h);
         }
-        const int crd[3] = {i, j, k};
-        int slab[3] = {-1, -1, -1};
-        if (pml) {
-#pragma unroll
-            for (int a = 0; a < 3; ++a) slab[a] = slab_own(crd[a], d.P, d.hi[a]);
-        }
         if (!ADJ) {
+            // psi^{ca} <- b psi^{ca} + a D_a u^c, one batch of loads per layer axis
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
                 if (slab[a] < 0) continue;
                 const unsigned q = slab_byte(d, a, slab[a], i, j, k);
+                T m[3];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) m[c] = ldb(d.mem[a][3 + c], q);
+                const T ca[2] = {d.pa[a][0][crd[a]], d.pa[a][1][crd[a]]};
+                const T cb[2] = {d.pb[a][0][crd[a]], d.pb[a][1][crd[a]]};
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
                     const int half = c != a;
-                    const T psi = d.pb[a][half][crd[a]] * ldb(d.mem[a][3 + c], q) + d.pa[a][half][crd[a]] * e[c][a];
+                    const T psi = cb[half] * m[c] + ca[half] * e[c][a];
                     stb(d.mem[a][3 + c], q, psi);
                     e[c][a] += psi;
                 }
             }
         }
-        const T lam = ldb(d.lam, o);
-        const T mz = ldb(d.mu, o + sz), mxz = ldb(d.mu, o + sx + sz), myz = ldb(d.mu, o + sy + sz);
-        const T mxy = ldb(d.mu, o + sx + sy);
-        const T m23 = harmonic4(m0, my, mz, myz);
-        const T m13 = harmonic4(m0, mx, mz, mxz);
-        const T m12 = harmonic4(m0, mx, my, mxy);
+        const T rz = rcp(mz), rxz = rcp(mxz), ryz = rcp(myz), rxy = rcp(mxy);
+        const T m23 = harmonic4r(r0, ry, rz, ryz);
+        const T m13 = harmonic4r(r0, rx, rz, rxz);
+        const T m12 = harmonic4r(r0, rx, ry, rxy);
         const T mu = m0;
         m0 = mz;
-        mx = mxz;
-        my = myz;
+        r0 = rz;
+        rx = rxz;
+        ry = ryz;
         const T tr = e[0][0] + e[1][1] + e[2][2];
-        const T sc = ADJ ? T(-1) : d.dt;
+        const T sc = ADJ ? T(-1) : dt;
         T w[6];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            w[c] = ldb(d.f[S11 + c], o) + sc * (lam * tr + T(2) * mu * e[c][c]);
-            stb(d.f[S11 + c], o, w[c]);
-        }
-        w[3] = ldb(d.f[S23], o) + sc * m23 * (e[1][2] + e[2][1]);
-        w[4] = ldb(d.f[S13], o) + sc * m13 * (e[0][2] + e[2][0]);
-        w[5] = ldb(d.f[S12], o) + sc * m12 * (e[0][1] + e[1][0]);
-        stb(d.f[S23], o, w[3]);
-        stb(d.f[S13], o, w[4]);
-        stb(d.f[S12], o, w[5]);
+        for (int c = 0; c < 3; ++c) w[c] = sold[c] + sc * (lam * tr + T(2) * mu * e[c][c]);
+        w[3] = sold[3] + sc * m23 * (e[1][2] + e[2][1]);
+        w[4] = sold[4] + sc * m13 * (e[0][2] + e[2][0]);
+        w[5] = sold[5] + sc * m12 * (e[0][1] + e[1][0]);
+#pragma unroll
+        for (int c = 0; c < 6; ++c) stb(d.f[S11 + c], o, w[c]);
         if (ADJ) {
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
@@ -335,11 +396,16 @@ __global__ __launch_bounds__(NT) void k_str(Dev<T> d, Tiles tl) {
                 // g = a psi~ <- b g + a dt w   (Delta^T s; the indicator is folded into a)
                 const unsigned q = slab_byte(d, a, slab[a], i, j, k);
                 const int tw = slab_twin(crd[a], d.P, d.hi[a]);
+                T m[3];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) m[c] = ldb(d.mem[a][3 + c], q);
+                const T ca[2] = {d.pa[a][0][crd[a]], d.pa[a][1][crd[a]]};
+                const T cb[2] = {d.pb[a][0][crd[a]], d.pb[a][1][crd[a]]};
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
                     const int half = c != a;
                     const int wi = c == a ? c : (c + a == 3 ? 3 : (c + a == 2 ? 4 : 5));
-                    const T g = d.pb[a][half][crd[a]] * ldb(d.mem[a][3 + c], q) + d.pa[a][half][crd[a]] * d.dt * w[wi];
+                    const T g = cb[half] * m[c] + ca[half] * dt * w[wi];
                     stb(d.mem[a][3 + c], q, g);
                     if (tw >= 0) stb(d.mem[a][3 + c], slab_byte(d, a, tw, i, j, k), g);
                 }

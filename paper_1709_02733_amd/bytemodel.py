@@ -9,17 +9,18 @@ each axis where the layer coefficient a is non-zero.
 Per cell of the volume (es = bytes per element, 4 for float):
   velocity      reads s x6, u x3, rho, alpha;   writes u x3     -> 14 es
   stress        reads u x3, s x6, lambda, mu;   writes s x6     -> 17 es
-  adj_velocity  reads s x6, q x3, lambda, mu, alpha; writes q x3 -> 15 es
-  adj_stress    reads q x3, s x6, rho;          writes s x6     -> 16 es
+  adj_velocity  reads w x6, r x3, rho, alpha;   writes r x3     -> 14 es
+  adj_stress    reads r x3, w x6, lambda, mu;   writes w x6     -> 17 es
+(the adjoint state is r = Q^-1 q and w = C s, so its passes have the forward shapes).
 Per C-PML cell of each axis:
   velocity / stress          phi (psi) x3 read + x3 written        ->  6 es
-  adj_velocity / adj_stress  psi~ (phi~) x3 read, phi~ (psi~) x3 read + written -> 9 es
+  adj_velocity / adj_stress  a psi~ (a phi~) x3 read, a phi~ (a psi~) x3 read + written -> 9 es
 Receivers: gather 24 + 8 + 8 bytes per (receiver, corner) plus 8 per trace
 sample; scatter the same per entry.
 """
 from __future__ import annotations
 
-PER_CELL = {"velocity": 14, "stress": 17, "adj_velocity": 15, "adj_stress": 16}
+PER_CELL = {"velocity": 14, "stress": 17, "adj_velocity": 14, "adj_stress": 17}
 PER_PML_CELL = {"velocity": 6, "stress": 6, "adj_velocity": 9, "adj_stress": 9}
 
 

@@ -115,22 +115,35 @@ Tiles make_tiles(int nx, int ny, int nz) {
     t.zc = (nz + t.nzc - 1) / t.nzc;
     t.nzc = (nz + t.zc - 1) / t.zc;
     t.ntiles = t.ntx * t.nty * t.nzc;
-    const int run = std::max(1, (t.ntiles + 511) / 512);
-    const int nruns = (t.ntiles + run - 1) / run;
-    // XCD x receives runs x, x + 8, ...; the first XCDs may hold one run more
-    const int runs_per = (nruns + 7) / 8;
-    t.per = runs_per * run;
     t.order = nullptr;
+    t.per = 0;
+    std::vector<int> cnt(8, 0);
+    for (int q = 0; q < t.ntiles; ++q) ++cnt[tile_xcd(t, q)];
+    for (int x = 0; x < 8; ++x) t.per = std::max(t.per, cnt[x]);
     return t;
 }
 
-std::vector<int> tile_order(const Tiles &t) {
+// XCD of a tile.  With at least eight tile rows and eight z chunks, the rows and chunks are
+// cut into eight bands each and region (y band, z band) goes to XCD (y band + z band) mod 8:
+// a Latin square, so every XCD holds one region of every y band and of every z band (the
+// same share of the C-PML layers of y and z; every region spans the x extent) and a
+// region's tiles share one L2.  Smaller grids deal runs of about ntiles / 512 tiles in
+// z-major order round-robin.
+int tile_xcd(const Tiles &t, int q) {
+    const int bx = q % t.ntx, r = q / t.ntx, by = r % t.nty, bz = r / t.nty;
+    (void)bx;
+    if (t.nty >= 8 && t.nzc >= 8) return (by * 8 / t.nty + bz * 8 / t.nzc) % 8;
     const int run = std::max(1, (t.ntiles + 511) / 512);
+    return (q / run) % 8;
+}
+
+std::vector<int> tile_order(const Tiles &t) {
     std::vector<int> order((size_t)8 * t.per, -1);
     std::vector<int> fill(8, 0);
-    for (int r = 0, first = 0; first < t.ntiles; ++r, first += run) {
-        const int x = r % 8;
-        for (int q = first; q < std::min(first + run, t.ntiles); ++q) order[(size_t)fill[x]++ * 8 + x] = q;
+    // tiles of an XCD in z-major order: a region's tiles are consecutive
+    for (int q = 0; q < t.ntiles; ++q) {
+        const int x = tile_xcd(t, q);
+        order[(size_t)fill[x]++ * 8 + x] = q;
     }
     return order;
 }

@@ -85,10 +85,19 @@ __host__ __device__ inline int slab_twin(int c, int P, int hi) {
 __host__ __device__ inline int slab_near(int c, int P, int hi) {
     return c <= P + 2 ? slab_lo(c) : (c >= hi - 2 ? slab_hi(c, P, hi) : -1);
 }
+// Element order: axis x as [side][k][j][s'] with s' the coordinate within the side's
+// P + 7 planes (a tile's rows of one side are contiguous; the two sides are touched by
+// different tiles), axis y as [k][s][i], axis z as [s][j][i].
 template <typename T>
 __device__ inline unsigned slab_byte(const Dev<T> &d, int axis, int s, int i, int j, int k) {
-    const unsigned e = axis == 0 ? ((unsigned)k * d.ny + j) * d.W + s
-                                 : (axis == 1 ? ((unsigned)k * d.W + s) * d.nx + i : ((unsigned)s * d.ny + j) * d.nx + i);
+    unsigned e;
+    if (axis == 0) {
+        const int hw = d.W >> 1;
+        const int side = s >= hw ? 1 : 0;
+        e = (((unsigned)side * d.nz + k) * d.ny + j) * hw + (s - side * hw);
+    } else {
+        e = axis == 1 ? ((unsigned)k * d.W + s) * d.nx + i : ((unsigned)s * d.ny + j) * d.nx + i;
+    }
     return e * (unsigned)sizeof(T);
 }
 // byte stride between neighbouring slab coordinates of an axis
@@ -107,10 +116,10 @@ struct Tiles {
     const int *order;        // device: tile of each block (-1 for a padding block)
 };
 Tiles make_tiles(int nx, int ny, int nz);
-// Tile of each block: tiles in z-major order are cut into runs of about ntiles / 512
-// tiles and the runs are dealt round-robin to the eight XCDs (block b runs on XCD b % 8),
-// so every XCD receives contiguous runs from all over the volume: the same share of
-// C-PML layer cells and of interior cells, with neighbouring tiles of a run in one L2.
+// XCD (0..7) that processes tile q; blocks run on XCD blockIdx % 8.
+int tile_xcd(const Tiles &t, int q);
+// Tile of each block (8 * per entries, -1 for padding blocks): the tiles of XCD x in z-major
+// order at entries x, x + 8, x + 16, ...
 std::vector<int> tile_order(const Tiles &t);
 
 // Receiver tables (cell offsets are padded element indices).

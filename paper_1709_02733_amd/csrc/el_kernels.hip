@@ -30,6 +30,7 @@ __global__ void k_convert_maps(Dev<T> d, const float *lam, const float *mu, cons
             const long long src = min(x, d.nx - 1) + (long long)d.nx * (min(y, d.ny - 1) + (long long)d.ny * min(z, d.nz - 1));
             vl = T(lam[src]);
             vm = T(mu[src]);
+            if (vm == T(0)) vm = T(0);   // -0 -> +0: the stencils take 1/mu, which must be +inf
             vr = T(rho[src]);
             va = T(alpha[src]);
         }

@@ -126,6 +126,24 @@ def test_forward_is_deterministic():
     assert torch.equal(plan.adjoint(y).clone(), plan.adjoint(y).clone())
 
 
+def test_negative_zero_shear_modulus():
+    """A fluid cell given as mu = -0.0 behaves as mu = +0.0: the staggered harmonic means
+    of the shear modulus are zero next to it (Sec. 2.2), results match the oracle and are
+    bitwise those of the same medium with +0.0."""
+    sc = S.random_scenario((23, 19, 17), seed=12, nsteps=40, npml=3, nrec=9, fluid_fraction=0.5)
+    assert (sc.mu == 0).any() and (sc.mu > 0).any()
+    neg = S.random_scenario((23, 19, 17), seed=12, nsteps=40, npml=3, nrec=9, fluid_fraction=0.5)
+    neg.mu = np.where(neg.mu == 0, np.float32(-0.0), neg.mu).astype(np.float32)
+    assert np.signbit(neg.mu[neg.mu == 0]).all()
+    p = torch.from_numpy(sc.p0)
+    a = el.Plan.from_scenario(sc).forward(p).cpu()
+    b = el.Plan.from_scenario(neg).forward(p).cpu()
+    assert torch.isfinite(b).all()
+    assert torch.equal(a, b)
+    ref = Model.from_scenario(sc).forward(sc.p0.astype(np.float64))
+    assert rel_l2(b.numpy(), ref) <= TOL32
+
+
 def test_receivers_on_faces_and_corners():
     sc = S.random_scenario((14, 12, 10), seed=11, nsteps=15, npml=2, nrec=1)
     rec = np.array([[0, 0, 0], [13, 11, 9], [13, 0, 4.5], [6.5, 11, 0], [0.25, 5.75, 9]]) * sc.dx

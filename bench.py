@@ -18,6 +18,7 @@ import hashlib
 import json
 import os
 import platform
+import re
 import sys
 import time
 
@@ -35,11 +36,15 @@ def log(*a):
 
 
 def kernel_source_sha1() -> str:
-    """Hash of the stencil kernels' sources (the counters are valid for this version only)."""
+    """Hash of the stencil kernels' sources with comments and blank space removed (the
+    counters are valid for this version of the code only)."""
     h = hashlib.sha1()
     for fn in KERNEL_SRCS:
-        with open(fn, "rb") as f:
-            h.update(f.read())
+        with open(fn) as f:
+            text = f.read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", "", text)
+        h.update(" ".join(text.split()).encode())
     return h.hexdigest()
 
 

@@ -33,9 +33,10 @@
 // the tiles processed next to it keep them in L1/L2.  There is no LDS and no
 // barrier.  The padded volume layout (see el_impl.h) makes every tap a plain
 // load: addresses are a 32-bit byte offset, shared by all fields, from the
-// field's base pointer.  Each block reads its tile from an order table that
-// gives every XCD (block id mod 8) contiguous runs of tiles from all over the
-// volume, so the C-PML layers are shared evenly among the XCDs.
+// field's base pointer.  Each block reads its tile from an order table (built
+// by tile_order on the host) that gives every XCD (block id mod 8) contiguous
+// regions of tiles spread over the volume, so every XCD holds the same share of
+// the C-PML layers and a region's neighbouring tiles share one L2.
 #include "el_impl.h"
 
 namespace el {

@@ -95,7 +95,11 @@ bool layout(const el_grid &g, int nrec, Layout *L) {
     L->csr_w = take(E * 8);
     L->stats = take(16 * 8);
     L->counter = take(256);
-    L->tile_order = take((size_t)8 * make_tiles(g.nx, g.ny, g.nz).per * sizeof(int));
+    {
+        const Tiles t = make_tiles(g.nx, g.ny, g.nz);
+        L->tile_order = take((size_t)8 * t.per * sizeof(int));
+        L->tile_flags = take((size_t)t.ntiles);
+    }
     L->partial = take(7 * kDotBlocks * 8);
     L->total = off;
     return true;
@@ -137,13 +141,13 @@ int tile_xcd(const Tiles &t, int q) {
     return (q / run) % 8;
 }
 
-std::vector<int> tile_order(const Tiles &t) {
+std::vector<int> tile_order(const Tiles &t, const unsigned char *fast) {
     std::vector<int> order((size_t)8 * t.per, -1);
     std::vector<int> fill(8, 0);
     // tiles of an XCD in z-major order: a region's tiles are consecutive
     for (int q = 0; q < t.ntiles; ++q) {
         const int x = tile_xcd(t, q);
-        order[(size_t)fill[x]++ * 8 + x] = q;
+        order[(size_t)fill[x]++ * 8 + x] = q | (fast && fast[q] ? kFastTile : 0);
     }
     return order;
 }
@@ -371,6 +375,16 @@ el_status upload_receivers(el_plan_ *p, const double *rec, hipStream_t s) {
     return EL_OK;
 }
 
+// Upload the tile order table, with the fluid flags when the fluid update is enabled.
+el_status upload_order(el_plan p, hipStream_t s) {
+    const std::vector<int> order = tile_order(p->tiles, p->fluid_path ? p->fast.data() : nullptr);
+    int *dst = reinterpret_cast<int *>(p->ws + p->L.tile_order);
+    HIP_TRY(hipMemcpyAsync(dst, order.data(), order.size() * sizeof(int), hipMemcpyHostToDevice, s), "tile order");
+    HIP_TRY(hipStreamSynchronize(s), "tile order");
+    p->tiles.order = dst;
+    return EL_OK;
+}
+
 el_status check_plan(el_plan p) {
     if (!p) return fail(EL_EINVAL, "plan is NULL");
     int dev = -1;
@@ -505,12 +519,25 @@ el_status el_plan_create(el_plan *out, const el_grid *grid, const float *lam, co
     st = upload_receivers(p, rec, s);
     if (st != EL_OK) return bail(st);
     {
-        const std::vector<int> order = tile_order(p->tiles);
-        int *dst = reinterpret_cast<int *>(p->ws + L.tile_order);
-        e = hipMemcpyAsync(dst, order.data(), order.size() * sizeof(int), hipMemcpyHostToDevice, s);
+        // fluid tiles (el_kernels.hip, k_classify), then the order table
+        unsigned char *flags = reinterpret_cast<unsigned char *>(p->ws + L.tile_flags);
+        e = grid->precision == EL_F64 ? launch_classify(p->dd, p->tiles, flags, s)
+                                      : launch_classify(p->df, p->tiles, flags, s);
+        p->fast.assign(p->tiles.ntiles, 0);
+        if (e == hipSuccess && p->tiles.ntiles > 0)
+            e = hipMemcpyAsync(p->fast.data(), flags, p->fast.size(), hipMemcpyDeviceToHost, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
-        if (e != hipSuccess) return bail(hip_fail(e, "tile order"));
-        p->tiles.order = dst;
+        if (e != hipSuccess) return bail(hip_fail(e, "fluid tiles"));
+        const Tiles &t = p->tiles;
+        for (int q = 0; q < t.ntiles; ++q) {
+            if (!p->fast[q]) continue;
+            const int bx = q % t.ntx, r = q / t.ntx, by = r % t.nty, bz = r / t.nty;
+            p->fast_tiles += 1;
+            p->fast_cells += (long long)(std::min(kTileX, grid->nx - bx * kTileX)) *
+                             std::min(kTileY, grid->ny - by * kTileY) * std::min(t.zc, grid->nz - bz * t.zc);
+        }
+        st = upload_order(p, s);
+        if (st != EL_OK) return bail(st);
     }
     e = hipStreamSynchronize(s);
     if (e != hipSuccess) return bail(hip_fail(e, "plan set-up"));
@@ -618,6 +645,21 @@ el_status el_plan_layout(el_plan p, int64_t *row_pitch, int64_t *plane_pitch, in
     if (row_pitch) *row_pitch = v.px;
     if (plane_pitch) *plane_pitch = v.plane;
     if (origin) *origin = v.origin;
+    return EL_OK;
+}
+
+el_status el_plan_fluid_path(el_plan p, int32_t enable, int64_t *fast_tiles, int64_t *fast_cells) {
+    el_status st = check_plan(p);
+    if (st != EL_OK) return st;
+    if (enable != -1 && enable != 0 && enable != 1) return fail(EL_EINVAL, "enable must be -1, 0 or 1");
+    if (enable >= 0 && (enable != 0) != p->fluid_path) {
+        HIP_TRY(hipEventSynchronize(p->done), "wait for the plan's previous operation");
+        p->fluid_path = enable != 0;
+        st = upload_order(p, nullptr);
+        if (st != EL_OK) return st;
+    }
+    if (fast_tiles) *fast_tiles = p->fluid_path ? p->fast_tiles : 0;
+    if (fast_cells) *fast_cells = p->fluid_path ? p->fast_cells : 0;
     return EL_OK;
 }
 

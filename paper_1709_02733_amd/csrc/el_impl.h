@@ -119,8 +119,10 @@ Tiles make_tiles(int nx, int ny, int nz);
 // XCD (0..7) that processes tile q; blocks run on XCD blockIdx % 8.
 int tile_xcd(const Tiles &t, int q);
 // Tile of each block (8 * per entries, -1 for padding blocks): the tiles of XCD x in z-major
-// order at entries x, x + 8, x + 16, ...
-std::vector<int> tile_order(const Tiles &t);
+// order at entries x, x + 8, x + 16, ...  An entry carries kFastTile when fast[q] is set
+// (fast may be null): the block then runs the fluid update of the tile.
+constexpr int kFastTile = 1 << 30;
+std::vector<int> tile_order(const Tiles &t, const unsigned char *fast);
 
 // Receiver tables (cell offsets are padded element indices).
 struct Rec {
@@ -146,6 +148,7 @@ struct Layout {
     size_t stats;            // media statistics (16 doubles)
     size_t counter;          // device step counter of captured step graphs
     size_t tile_order;       // tile of each stencil block
+    size_t tile_flags;       // per tile: 1 if the fluid update applies
     size_t partial;          // reduction partials
     size_t total;
 };
@@ -160,6 +163,8 @@ template <typename T> hipError_t launch_convert_maps(const Dev<T> &d, const floa
 hipError_t launch_media_stats(const float *lam, const float *mu, const float *rho, const float *alpha,
                               long long n, double dt, double *stats, double *partial, hipStream_t s);
 template <typename T> hipError_t launch_zero_state(const Dev<T> &d, hipStream_t s);
+template <typename T> hipError_t launch_classify(const Dev<T> &d, const Tiles &tl, unsigned char *fast,
+                                                 hipStream_t s);
 template <typename T> hipError_t launch_inject(const Dev<T> &d, const T *p0, hipStream_t s);
 template <typename T> hipError_t launch_velocity(const Dev<T> &d, const Tiles &tl, hipStream_t s);
 template <typename T> hipError_t launch_stress(const Dev<T> &d, const Tiles &tl, hipStream_t s);
@@ -190,6 +195,9 @@ struct el_plan_ {
     el::Dev<double> dd;
     el::Rec rec;
     el::Tiles tiles;
+    std::vector<unsigned char> fast;   // per tile: the fluid update applies (host copy)
+    long long fast_tiles = 0, fast_cells = 0;
+    bool fluid_path = true;            // use the fluid update where it applies
     hipEvent_t done;
     double cmax;
     // benchmark instrumentation: per kernel kind, event pairs and how many are in use

@@ -133,6 +133,48 @@ hipError_t launch_zero_state(const Dev<T> &d, hipStream_t s) {
     return hipGetLastError();
 }
 
+// Fluid tiles.  Where mu = 0 the stress update keeps s11 = s22 = s33 and leaves the shear
+// stresses at zero (their edge moduli are harmonic means that vanish next to a fluid cell),
+// in both operators (forward: sigma; adjoint: w = C s).  A tile whose cells and the cells
+// within two of them are all fluid, and whose cells are outside the reach of every C-PML
+// layer, can therefore be updated from the normal stress s11 alone.  One block per tile
+// checks mu over that box; cells outside the grid count as fluid (zero extension).
+template <typename T>
+__global__ void k_classify(Dev<T> d, Tiles tl, unsigned char *fast) {
+    const int q = blockIdx.x;
+    if (q >= tl.ntiles) return;
+    const int bx = q % tl.ntx, r = q / tl.ntx, by = r % tl.nty, bz = r / tl.nty;
+    const int x0 = bx * kTileX, y0 = by * kTileY, z0 = bz * tl.zc;
+    const int x1 = min(x0 + kTileX, d.nx), y1 = min(y0 + kTileY, d.ny), z1 = min(z0 + tl.zc, d.nz);
+    bool ok = true;
+    if (d.P > 0) {
+        // slab_near < 0 along every axis for every cell: c > P + 2 and c < hi - 2
+        ok = x0 > d.P + 2 && x1 - 1 < d.hi[0] - 2 && y0 > d.P + 2 && y1 - 1 < d.hi[1] - 2 && z0 > d.P + 2 &&
+             z1 - 1 < d.hi[2] - 2;
+    }
+    int solid = 0;
+    if (ok) {
+        const int ax = max(x0 - 2, 0), ay = max(y0 - 2, 0), az = max(z0 - 2, 0);
+        const int w = min(x1 + 2, d.nx) - ax, hgt = min(y1 + 2, d.ny) - ay, dep = min(z1 + 2, d.nz) - az;
+        const long long n = (long long)w * hgt * dep;
+        for (long long e = threadIdx.x; e < n; e += blockDim.x) {
+            const int xx = ax + (int)(e % w);
+            const long long rr = e / w;
+            const int yy = ay + (int)(rr % hgt), zz = az + (int)(rr / hgt);
+            if (d.mu[(long long)(zz + 2) * d.plane + (long long)yy * d.px + xx] != T(0)) solid = 1;
+        }
+    }
+    solid = __syncthreads_or(solid);
+    if (threadIdx.x == 0) fast[q] = (ok && !solid) ? 1 : 0;
+}
+
+template <typename T>
+hipError_t launch_classify(const Dev<T> &d, const Tiles &tl, unsigned char *fast, hipStream_t s) {
+    if (tl.ntiles == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_classify<T>, dim3(tl.ntiles), dim3(256), 0, s, d, tl, fast);
+    return hipGetLastError();
+}
+
 // Padded element of cell number q (x fastest).
 template <typename T>
 __device__ __forceinline__ long long padded(const Dev<T> &d, long long q) {
@@ -353,6 +395,7 @@ hipError_t launch_dot(const T *a, const T *b, long long n, double *partial, doub
     template hipError_t launch_convert_maps<T>(const Dev<T> &, const float *, const float *, const float *,          \
                                                const float *, hipStream_t);                                          \
     template hipError_t launch_zero_state<T>(const Dev<T> &, hipStream_t);                                           \
+    template hipError_t launch_classify<T>(const Dev<T> &, const Tiles &, unsigned char *, hipStream_t);             \
     template hipError_t launch_inject<T>(const Dev<T> &, const T *, hipStream_t);                                    \
     template hipError_t launch_gather<T>(const Dev<T> &, const Rec &, double *, hipStream_t);                        \
     template hipError_t launch_scatter<T>(const Dev<T> &, const Rec &, const double *, hipStream_t);                 \

@@ -108,10 +108,13 @@ __device__ __forceinline__ T harmonic4r(T r0, T r1, T r2, T r3) {
     return T(4) * rcp(r0 + r1 + r2 + r3);
 }
 
-// Tile of this block from the XCD-balanced order table; false for padding blocks.
-__device__ __forceinline__ bool tile_of(const Tiles &tl, int nz, int &x0, int &y0, int &z0, int &z1) {
-    const int t = tl.order[blockIdx.x];
-    if (t < 0) return false;
+// Tile of this block from the XCD-balanced order table; false for padding blocks.  fast is
+// set for a fluid tile (see k_classify).
+__device__ __forceinline__ bool tile_of(const Tiles &tl, int nz, int &x0, int &y0, int &z0, int &z1, bool &fast) {
+    const int ent = tl.order[blockIdx.x];
+    if (ent < 0) return false;
+    fast = (ent & kFastTile) != 0;
+    const int t = ent & (kFastTile - 1);
     const int bx = t % tl.ntx;
     const int r = t / tl.ntx;
     const int by = r % tl.nty;
@@ -135,15 +138,67 @@ __device__ __forceinline__ bool tile_of(const Tiles &tl, int nz, int &x0, int &y
 //   axis z: c=0 s13 (Dm), c=1 s23 (Dm), c=2 s33 (Dp)
 // ------------------------------------------------------------------------
 template <typename T, bool ADJ>
-__global__ __launch_bounds__(NT) void k_vel(Dev<T> d, Tiles tl) {
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 5 : 1))) void k_vel(Dev<T> d, Tiles tl) {
     int x0, y0, z0, z1;
-    if (!tile_of(tl, d.nz, x0, y0, z0, z1)) return;
+    bool fast = false;
+    if (!tile_of(tl, d.nz, x0, y0, z0, z1, fast)) return;
     const int i = x0 + (int)threadIdx.x % TX, j = y0 + (int)threadIdx.x / TX;
     if (i >= d.nx || j >= d.ny) return;
     const T h = d.inv_dx, dt = d.dt;
     const unsigned sx = sizeof(T), sy = d.sy, sz = d.sz;
     const T *s11 = d.f[S11], *s22 = d.f[S22], *s33 = d.f[S33], *s23 = d.f[S23], *s13 = d.f[S13], *s12 = d.f[S12];
     unsigned o = d.origin + (unsigned)z0 * sz + (unsigned)j * sy + (unsigned)i * sx;
+    if (fast) {
+        // fluid tile: s22 = s33 = s11 and the shear stresses are zero on every tap, so the
+        // three nonzero differences are those of s11 along x, y and z
+        T qs[4];   // s11 at planes k-1..k+2
+        qs[0] = T(0);
+        qs[1] = ldb(s11, o - sz);
+        qs[2] = ldb(s11, o);
+        qs[3] = ldb(s11, o + sz);
+        T rho_k = ldb(d.rho, o), alp_k = ldb(d.alpha, o);
+        for (int k = z0; k < z1; ++k, o += sz) {
+#pragma unroll
+            for (int n = 0; n < 3; ++n) qs[n] = qs[n + 1];
+            qs[3] = ldb(s11, o + 2 * sz);
+            T a11[4], b11[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                a11[q] = ldb(s11, o + (unsigned)(q - 1) * sx);
+                b11[q] = ldb(s11, o + (unsigned)(q - 1) * sy);
+            }
+            T uold[3], rho_n[3], alp_n[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) uold[c] = ldb(d.f[U1 + c], o);
+            rho_n[0] = ldb(d.rho, o + sx);
+            rho_n[1] = ldb(d.rho, o + sy);
+            rho_n[2] = ldb(d.rho, o + sz);
+            alp_n[0] = ldb(d.alpha, o + sx);
+            alp_n[1] = ldb(d.alpha, o + sy);
+            alp_n[2] = ldb(d.alpha, o + sz);
+            __builtin_amdgcn_sched_barrier(0);
+            T acc[3];
+            acc[0] = dplus(a11[0], a11[1], a11[2], a11[3], h);
+            acc[1] = dplus(b11[0], b11[1], b11[2], b11[3], h);
+            acc[2] = dplus(qs[0], qs[1], qs[2], qs[3], h);
+            if (ADJ) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) acc[c] *= dt;
+            }
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const T rho_c = T(0.5) * (rho_k + rho_n[c]);
+                const T alp_c = T(0.5) * (alp_k + alp_n[c]);
+                const T irho = rcp(rho_c);
+                const T out = ADJ ? (T(1) - dt * alp_c) * uold[c] - acc[c] * irho
+                                  : (T(1) - dt * alp_c) * uold[c] + dt * irho * acc[c];
+                stb(d.f[U1 + c], o, out);
+            }
+            rho_k = rho_n[2];
+            alp_k = alp_n[2];
+        }
+        return;
+    }
     T qa[4], qb[4], qc[4];   // s13, s23 at planes k-2..k+1; s33 at planes k-1..k+2
     qa[0] = qb[0] = qc[0] = T(0);
     qa[1] = ldb(s13, o - 2 * sz);
@@ -275,15 +330,53 @@ __global__ __launch_bounds__(NT) void k_vel(Dev<T> d, Tiles tl) {
 //   axis x: c=0 Dm, c=1 Dp, c=2 Dp;  axis y: c=0 Dp, c=1 Dm, c=2 Dp;  axis z: c=0 Dp, c=1 Dp, c=2 Dm
 // ------------------------------------------------------------------------
 template <typename T, bool ADJ>
-__global__ __launch_bounds__(NT) void k_str(Dev<T> d, Tiles tl) {
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 5 : 1))) void k_str(Dev<T> d, Tiles tl) {
     int x0, y0, z0, z1;
-    if (!tile_of(tl, d.nz, x0, y0, z0, z1)) return;
+    bool fast = false;
+    if (!tile_of(tl, d.nz, x0, y0, z0, z1, fast)) return;
     const int i = x0 + (int)threadIdx.x % TX, j = y0 + (int)threadIdx.x / TX;
     if (i >= d.nx || j >= d.ny) return;
     const T h = d.inv_dx, dt = d.dt;
     const unsigned sx = sizeof(T), sy = d.sy, sz = d.sz;
     const T *u1 = d.f[U1], *u2 = d.f[U2], *u3 = d.f[U3];
     unsigned o = d.origin + (unsigned)z0 * sz + (unsigned)j * sy + (unsigned)i * sx;
+    if (fast) {
+        // fluid tile: mu = 0, so the three normal stresses take the same increment lambda tr
+        // and the shear stresses stay zero (not written)
+        T qc[4];   // u3 at planes k-2..k+1
+        qc[0] = T(0);
+        qc[1] = ldb(u3, o - 2 * sz);
+        qc[2] = ldb(u3, o - sz);
+        qc[3] = ldb(u3, o);
+        for (int k = z0; k < z1; ++k, o += sz) {
+#pragma unroll
+            for (int n = 0; n < 3; ++n) qc[n] = qc[n + 1];
+            qc[3] = ldb(u3, o + sz);
+            T a1[4], b2[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                a1[q] = ldb(u1, o + (unsigned)(q - 2) * sx);
+                b2[q] = ldb(u2, o + (unsigned)(q - 2) * sy);
+            }
+            const T sold = ldb(d.f[S11], o);
+            const T lam = ldb(d.lam, o);
+            __builtin_amdgcn_sched_barrier(0);
+            T e0 = dminus(a1[0], a1[1], a1[2], a1[3], h);
+            T e1 = dminus(b2[0], b2[1], b2[2], b2[3], h);
+            T e2 = dminus(qc[0], qc[1], qc[2], qc[3], h);
+            if (ADJ) {
+                e0 *= dt;
+                e1 *= dt;
+                e2 *= dt;
+            }
+            const T tr = e0 + e1 + e2;
+            const T w = sold + (ADJ ? T(-1) : dt) * (lam * tr);
+            stb(d.f[S11], o, w);
+            stb(d.f[S22], o, w);
+            stb(d.f[S33], o, w);
+        }
+        return;
+    }
     T qa[4], qb[4], qc[4];   // u1, u2 at planes k-1..k+2; u3 at planes k-2..k+1
     qa[0] = qb[0] = qc[0] = T(0);
     qa[1] = ldb(u1, o - sz);

@@ -39,7 +39,8 @@ class Grid(ctypes.Structure):
 _lib = None
 EXPORTS = ("el_version", "el_status_string", "el_last_error", "el_grid_check", "el_plan_bytes",
            "el_plan_create", "el_plan_destroy", "el_forward", "el_adjoint", "el_dot_f64",
-           "el_plan_field", "el_plan_layout", "el_plan_sizes", "el_plan_timing", "el_plan_kernel_time",
+           "el_plan_field", "el_plan_layout", "el_plan_sizes", "el_plan_fluid_path", "el_plan_timing",
+           "el_plan_kernel_time",
            "el_exec_create", "el_exec_destroy", "el_exec_start", "el_exec_poll", "el_exec_wait", "el_exec_slots")
 KERNELS = ("velocity", "stress", "adj_velocity", "adj_stress", "gather", "scatter")
 
@@ -78,6 +79,8 @@ def lib():
                                      ctypes.POINTER(ctypes.c_int64)]
         L.el_plan_sizes.restype = st
         L.el_plan_sizes.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(i32), ctypes.POINTER(i32)]
+        L.el_plan_fluid_path.restype = st
+        L.el_plan_fluid_path.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
         L.el_plan_timing.restype = st
         L.el_plan_timing.argtypes = [vp, i32]
         L.el_plan_kernel_time.restype = st
@@ -227,6 +230,14 @@ class Plan:
                                     ctypes.c_void_p(bb.data_ptr()), ctypes.c_void_p(out.data_ptr()),
                                     _stream(stream)))
         return out
+
+    def fluid_path(self, enable: bool | None = None) -> tuple[int, int]:
+        """Switch the fluid-tile update on or off (None keeps the setting); returns the number
+        of tiles and of cells that take it (el_plan_fluid_path)."""
+        tiles, cells = ctypes.c_int64(0), ctypes.c_int64(0)
+        flag = -1 if enable is None else (1 if enable else 0)
+        _check(lib().el_plan_fluid_path(self._h, flag, ctypes.byref(tiles), ctypes.byref(cells)))
+        return tiles.value, cells.value
 
     def timing(self, enable: bool = True):
         """Record an event pair around every time-loop kernel launch of later operations."""

@@ -144,6 +144,55 @@ def test_negative_zero_shear_modulus():
     assert rel_l2(b.numpy(), ref) <= TOL32
 
 
+def _fluid_ball_scenario(seed=13, nsteps=60):
+    """192 x 40 x 40 absorbing water (mu = 0) holding a solid ball of radius 6 cells: the
+    interior tiles away from the ball take the fluid update, the others the general one."""
+    sc = S.random_scenario((192, 40, 40), seed=seed, nsteps=nsteps, npml=4, nrec=24, fluid_fraction=1.0)
+    z, y, x = np.meshgrid(np.arange(40), np.arange(40), np.arange(192), indexing="ij")
+    ball = (x - 100) ** 2 + (y - 20) ** 2 + (z - 20) ** 2 <= 36
+    cp, cs, rho = 2800.0, 1500.0, 1850.0
+    sc.lam = np.where(ball, rho * (cp * cp - 2 * cs * cs), sc.lam).astype(np.float32)
+    sc.mu = np.where(ball, rho * cs * cs, sc.mu).astype(np.float32)
+    sc.rho = np.where(ball, rho, sc.rho).astype(np.float32)
+    sc.dt = 0.3 * sc.dx / cp
+    return sc
+
+
+@pytest.mark.parametrize("precision,tol_same,tol_ref", [("f32", 1e-6, TOL32), ("f64", 1e-13, TOL64)])
+def test_fluid_tiles_match_general_update_and_oracle(precision, tol_same, tol_ref):
+    """Tiles that are fluid with a two-cell margin are updated from s11 alone (the fluid limit,
+    Sec. 2.1): H and H^T equal the general update and the oracle."""
+    sc = _fluid_ball_scenario()
+    plan = el.Plan.from_scenario(sc, precision=precision)
+    tiles, cells = plan.fluid_path()
+    banner(f"fluid tiles {tiles}, cells {cells} of {sc.ncells}")
+    assert tiles > 0 and 0 < cells < sc.ncells
+    p = torch.from_numpy(sc.p0)
+    y = np.random.default_rng(3).standard_normal((sc.nsteps, sc.nrec))
+    tr_fast = plan.forward(p).cpu().numpy()
+    pa_fast = plan.adjoint(torch.from_numpy(y)).cpu().numpy().astype(np.float64)
+    assert plan.fluid_path(False) == (0, 0)
+    tr_gen = plan.forward(p).cpu().numpy()
+    pa_gen = plan.adjoint(torch.from_numpy(y)).cpu().numpy().astype(np.float64)
+    assert plan.fluid_path(True) == (tiles, cells)
+    banner(f"fluid vs general: traces bitwise {np.array_equal(tr_fast, tr_gen)}, "
+           f"max {rel_max(tr_fast, tr_gen):.2e}; adjoint bitwise {np.array_equal(pa_fast, pa_gen)}, "
+           f"max {rel_max(pa_fast, pa_gen):.2e}")
+    assert rel_max(tr_fast, tr_gen) <= tol_same and rel_max(pa_fast, pa_gen) <= tol_same
+    ref = Model.from_scenario(sc)
+    assert rel_l2(tr_fast, ref.forward(sc.p0.astype(np.float64))) <= tol_ref
+    assert rel_l2(pa_fast, ref.adjoint(y)) <= tol_ref
+
+
+def test_fluid_tiles_dot_product():
+    sc = _fluid_ball_scenario(seed=14, nsteps=80)
+    plan = el.Plan.from_scenario(sc)
+    assert plan.fluid_path()[0] > 0
+    r = _dot_residual(plan, sc, 5)
+    banner(f"dot residual with fluid tiles {r:.3e}")
+    assert r <= 1e-5
+
+
 def test_receivers_on_faces_and_corners():
     sc = S.random_scenario((14, 12, 10), seed=11, nsteps=15, npml=2, nrec=1)
     rec = np.array([[0, 0, 0], [13, 11, 9], [13, 0, 4.5], [6.5, 11, 0], [0.25, 5.75, 9]]) * sc.dx

@@ -136,9 +136,10 @@ hipError_t launch_zero_state(const Dev<T> &d, hipStream_t s) {
 // Fluid tiles.  Where mu = 0 the stress update keeps s11 = s22 = s33 and leaves the shear
 // stresses at zero (their edge moduli are harmonic means that vanish next to a fluid cell),
 // in both operators (forward: sigma; adjoint: w = C s).  A tile whose cells and the cells
-// within two of them are all fluid, and whose cells are outside the reach of every C-PML
-// layer, can therefore be updated from the normal stress s11 alone.  One block per tile
-// checks mu over that box; cells outside the grid count as fluid (zero extension).
+// within two of them are all fluid can therefore be updated from the normal stress s11
+// alone, with only the diagonal C-PML memory variables (a solid cell is at least three
+// cells from the tile, out of reach of its taps).  One block per tile checks mu over that
+// box; cells outside the grid count as fluid (zero extension).
 template <typename T>
 __global__ void k_classify(Dev<T> d, Tiles tl, unsigned char *fast) {
     const int q = blockIdx.x;
@@ -146,14 +147,8 @@ __global__ void k_classify(Dev<T> d, Tiles tl, unsigned char *fast) {
     const int bx = q % tl.ntx, r = q / tl.ntx, by = r % tl.nty, bz = r / tl.nty;
     const int x0 = bx * kTileX, y0 = by * kTileY, z0 = bz * tl.zc;
     const int x1 = min(x0 + kTileX, d.nx), y1 = min(y0 + kTileY, d.ny), z1 = min(z0 + tl.zc, d.nz);
-    bool ok = true;
-    if (d.P > 0) {
-        // slab_near < 0 along every axis for every cell: c > P + 2 and c < hi - 2
-        ok = x0 > d.P + 2 && x1 - 1 < d.hi[0] - 2 && y0 > d.P + 2 && y1 - 1 < d.hi[1] - 2 && z0 > d.P + 2 &&
-             z1 - 1 < d.hi[2] - 2;
-    }
     int solid = 0;
-    if (ok) {
+    {
         const int ax = max(x0 - 2, 0), ay = max(y0 - 2, 0), az = max(z0 - 2, 0);
         const int w = min(x1 + 2, d.nx) - ax, hgt = min(y1 + 2, d.ny) - ay, dep = min(z1 + 2, d.nz) - az;
         const long long n = (long long)w * hgt * dep;
@@ -165,7 +160,7 @@ __global__ void k_classify(Dev<T> d, Tiles tl, unsigned char *fast) {
         }
     }
     solid = __syncthreads_or(solid);
-    if (threadIdx.x == 0) fast[q] = (ok && !solid) ? 1 : 0;
+    if (threadIdx.x == 0) fast[q] = solid ? 0 : 1;
 }
 
 template <typename T>

@@ -148,9 +148,14 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
     const unsigned sx = sizeof(T), sy = d.sy, sz = d.sz;
     const T *s11 = d.f[S11], *s22 = d.f[S22], *s33 = d.f[S33], *s23 = d.f[S23], *s13 = d.f[S13], *s12 = d.f[S12];
     unsigned o = d.origin + (unsigned)z0 * sz + (unsigned)j * sy + (unsigned)i * sx;
+    const bool pml = d.P > 0;
+    const int snx = pml ? slab_near(i, d.P, d.hi[0]) : -1, sny = pml ? slab_near(j, d.P, d.hi[1]) : -1;
+    const int sox = pml ? slab_own(i, d.P, d.hi[0]) : -1, soy = pml ? slab_own(j, d.P, d.hi[1]) : -1;
     if (fast) {
         // fluid tile: s22 = s33 = s11 and the shear stresses are zero on every tap, so the
-        // three nonzero differences are those of s11 along x, y and z
+        // three nonzero differences are those of s11 along x, y and z.  Of the C-PML memory
+        // variables only the diagonal ones (phi^{cc}; in the adjoint a psi~^{cc} and
+        // a phi~^{cc}) act on fluid cells: the others stay zero or meet only zero moduli.
         T qs[4];   // s11 at planes k-1..k+2
         qs[0] = T(0);
         qs[1] = ldb(s11, o - sz);
@@ -181,21 +186,50 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
             acc[0] = dplus(a11[0], a11[1], a11[2], a11[3], h);
             acc[1] = dplus(b11[0], b11[1], b11[2], b11[3], h);
             acc[2] = dplus(qs[0], qs[1], qs[2], qs[3], h);
+            const int crd[3] = {i, j, k};
+            const int slab[3] = {sox, soy, pml ? slab_own(k, d.P, d.hi[2]) : -1};
             if (ADJ) {
 #pragma unroll
                 for (int c = 0; c < 3; ++c) acc[c] *= dt;
+                const int near[3] = {snx, sny, pml ? slab_near(k, d.P, d.hi[2]) : -1};
+#pragma unroll
+                for (int a = 0; a < 3; ++a)
+                    if (near[a] >= 0)
+                        acc[a] += dp_at(d.mem[a][3 + a], slab_byte(d, a, near[a], i, j, k), slab_stride(d, a), h);
+            } else {
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    if (slab[a] < 0) continue;
+                    const unsigned q = slab_byte(d, a, slab[a], i, j, k);
+                    const T phi = d.pb[a][1][crd[a]] * ldb(d.mem[a][a], q) + d.pa[a][1][crd[a]] * acc[a];
+                    stb(d.mem[a][a], q, phi);
+                    acc[a] += phi;
+                }
             }
+            T out[3];
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 const T rho_c = T(0.5) * (rho_k + rho_n[c]);
                 const T alp_c = T(0.5) * (alp_k + alp_n[c]);
                 const T irho = rcp(rho_c);
-                const T out = ADJ ? (T(1) - dt * alp_c) * uold[c] - acc[c] * irho
-                                  : (T(1) - dt * alp_c) * uold[c] + dt * irho * acc[c];
-                stb(d.f[U1 + c], o, out);
+                out[c] = ADJ ? (T(1) - dt * alp_c) * uold[c] - acc[c] * irho
+                             : (T(1) - dt * alp_c) * uold[c] + dt * irho * acc[c];
+                stb(d.f[U1 + c], o, out[c]);
             }
             rho_k = rho_n[2];
             alp_k = alp_n[2];
+            if (ADJ) {
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    if (slab[a] < 0) continue;
+                    // g' = a phi~^{aa} <- b g' + a dt r^a
+                    const unsigned q = slab_byte(d, a, slab[a], i, j, k);
+                    const int tw = slab_twin(crd[a], d.P, d.hi[a]);
+                    const T g = d.pb[a][1][crd[a]] * ldb(d.mem[a][a], q) + d.pa[a][1][crd[a]] * dt * out[a];
+                    stb(d.mem[a][a], q, g);
+                    if (tw >= 0) stb(d.mem[a][a], slab_byte(d, a, tw, i, j, k), g);
+                }
+            }
         }
         return;
     }
@@ -211,9 +245,6 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
     qc[2] = ldb(s33, o);
     qc[3] = ldb(s33, o + sz);
     T rho_k = ldb(d.rho, o), alp_k = ldb(d.alpha, o);
-    const bool pml = d.P > 0;
-    const int snx = pml ? slab_near(i, d.P, d.hi[0]) : -1, sny = pml ? slab_near(j, d.P, d.hi[1]) : -1;
-    const int sox = pml ? slab_own(i, d.P, d.hi[0]) : -1, soy = pml ? slab_own(j, d.P, d.hi[1]) : -1;
     for (int k = z0; k < z1; ++k, o += sz) {
 #pragma unroll
         for (int n = 0; n < 3; ++n) {
@@ -340,9 +371,13 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
     const unsigned sx = sizeof(T), sy = d.sy, sz = d.sz;
     const T *u1 = d.f[U1], *u2 = d.f[U2], *u3 = d.f[U3];
     unsigned o = d.origin + (unsigned)z0 * sz + (unsigned)j * sy + (unsigned)i * sx;
+    const bool pml = d.P > 0;
+    const int snx = pml ? slab_near(i, d.P, d.hi[0]) : -1, sny = pml ? slab_near(j, d.P, d.hi[1]) : -1;
+    const int sox = pml ? slab_own(i, d.P, d.hi[0]) : -1, soy = pml ? slab_own(j, d.P, d.hi[1]) : -1;
     if (fast) {
         // fluid tile: mu = 0, so the three normal stresses take the same increment lambda tr
-        // and the shear stresses stay zero (not written)
+        // and the shear stresses stay zero (not written).  Only the diagonal C-PML memory
+        // variables (psi^{cc}; in the adjoint a phi~^{cc} and a psi~^{cc}) act on the trace.
         T qc[4];   // u3 at planes k-2..k+1
         qc[0] = T(0);
         qc[1] = ldb(u3, o - 2 * sz);
@@ -361,19 +396,47 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
             const T sold = ldb(d.f[S11], o);
             const T lam = ldb(d.lam, o);
             __builtin_amdgcn_sched_barrier(0);
-            T e0 = dminus(a1[0], a1[1], a1[2], a1[3], h);
-            T e1 = dminus(b2[0], b2[1], b2[2], b2[3], h);
-            T e2 = dminus(qc[0], qc[1], qc[2], qc[3], h);
+            T e[3];
+            e[0] = dminus(a1[0], a1[1], a1[2], a1[3], h);
+            e[1] = dminus(b2[0], b2[1], b2[2], b2[3], h);
+            e[2] = dminus(qc[0], qc[1], qc[2], qc[3], h);
+            const int crd[3] = {i, j, k};
+            const int slab[3] = {sox, soy, pml ? slab_own(k, d.P, d.hi[2]) : -1};
             if (ADJ) {
-                e0 *= dt;
-                e1 *= dt;
-                e2 *= dt;
+#pragma unroll
+                for (int a = 0; a < 3; ++a) e[a] *= dt;
+                const int near[3] = {snx, sny, pml ? slab_near(k, d.P, d.hi[2]) : -1};
+#pragma unroll
+                for (int a = 0; a < 3; ++a)
+                    if (near[a] >= 0)
+                        e[a] += dm_at(d.mem[a][a], slab_byte(d, a, near[a], i, j, k), slab_stride(d, a), h);
+            } else {
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    if (slab[a] < 0) continue;
+                    const unsigned q = slab_byte(d, a, slab[a], i, j, k);
+                    const T psi = d.pb[a][0][crd[a]] * ldb(d.mem[a][3 + a], q) + d.pa[a][0][crd[a]] * e[a];
+                    stb(d.mem[a][3 + a], q, psi);
+                    e[a] += psi;
+                }
             }
-            const T tr = e0 + e1 + e2;
+            const T tr = e[0] + e[1] + e[2];
             const T w = sold + (ADJ ? T(-1) : dt) * (lam * tr);
             stb(d.f[S11], o, w);
             stb(d.f[S22], o, w);
             stb(d.f[S33], o, w);
+            if (ADJ) {
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    if (slab[a] < 0) continue;
+                    // g = a psi~^{aa} <- b g + a dt w_aa
+                    const unsigned q = slab_byte(d, a, slab[a], i, j, k);
+                    const int tw = slab_twin(crd[a], d.P, d.hi[a]);
+                    const T g = d.pb[a][0][crd[a]] * ldb(d.mem[a][3 + a], q) + d.pa[a][0][crd[a]] * dt * w;
+                    stb(d.mem[a][3 + a], q, g);
+                    if (tw >= 0) stb(d.mem[a][3 + a], slab_byte(d, a, tw, i, j, k), g);
+                }
+            }
         }
         return;
     }
@@ -392,9 +455,6 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
     // (carried from the previous plane)
     T m0 = ldb(d.mu, o);
     T r0 = rcp(m0), rx = rcp(ldb(d.mu, o + sx)), ry = rcp(ldb(d.mu, o + sy));
-    const bool pml = d.P > 0;
-    const int snx = pml ? slab_near(i, d.P, d.hi[0]) : -1, sny = pml ? slab_near(j, d.P, d.hi[1]) : -1;
-    const int sox = pml ? slab_own(i, d.P, d.hi[0]) : -1, soy = pml ? slab_own(j, d.P, d.hi[1]) : -1;
     for (int k = z0; k < z1; ++k, o += sz) {
 #pragma unroll
         for (int n = 0; n < 3; ++n) {

@@ -183,18 +183,22 @@ el_status el_plan_sizes(el_plan plan, int64_t *ncells, int32_t *nrec, int32_t *n
  * stresses equal and the shear stresses at zero; the same holds for the
  * adjoint state w = C s.  At plan creation every stencil tile (64 x 4 cells
  * by a chunk of z planes) whose cells, and the cells within two of them,
- * all have mu = 0 and whose cells are out of reach of every C-PML layer is
- * marked, and the stencil passes update such tiles from the normal stress
- * s11 alone: fewer bytes, the same results (the shear stresses are not
+ * all have mu = 0 is marked, and the stencil passes update such tiles from
+ * the normal stress s11 alone, with only the diagonal C-PML memory
+ * variables: fewer bytes, the same results (the shear stresses are not
  * written, s22 and s33 receive the value of s11).
  *   enable: 1 use the fluid update where it applies (the default), 0 never,
  *           -1 keep the current setting.  A change waits for the plan's
  *           previous operation (host-blocking).
  *   *fast_tiles, *fast_cells (host, may be NULL): tiles and cells that take
  *           the fluid update under the resulting setting.
+ *   *fast_layer_cells (host, may be NULL): the sum over the three axes of
+ *           those cells that lie in the axis's C-PML layers (depth > 0); the
+ *           fluid update carries only the diagonal memory variable there.
  * Errors: EL_EINVAL for a NULL plan or an enable outside -1..1.
  */
-el_status el_plan_fluid_path(el_plan plan, int32_t enable, int64_t *fast_tiles, int64_t *fast_cells);
+el_status el_plan_fluid_path(el_plan plan, int32_t enable, int64_t *fast_tiles, int64_t *fast_cells,
+                             int64_t *fast_layer_cells);
 
 /* Kernel kinds reported by el_plan_kernel_time(). */
 #define EL_K_VELOCITY     0   /* forward velocity pass (+ phi slabs)           */

@@ -15,10 +15,13 @@ Per cell of the volume (es = bytes per element, 4 for float):
 Per C-PML cell of each axis:
   velocity / stress          phi (psi) x3 read + x3 written        ->  6 es
   adj_velocity / adj_stress  a psi~ (a phi~) x3 read, a phi~ (a psi~) x3 read + written -> 9 es
-Per cell of a fluid tile (mu = 0 on the tile and two cells around it, out of the
-C-PML), where s22 = s33 = s11 and the shear stresses are zero:
+Per cell of a fluid tile (mu = 0 on the tile and two cells around it), where
+s22 = s33 = s11 and the shear stresses are zero:
   velocity / adj_velocity  reads s11, u x3, rho, alpha; writes u x3              ->  9 es
   stress / adj_stress      reads u x3, s11, lambda;     writes s11, s22, s33      ->  8 es
+and per fluid cell of each axis's C-PML layers only the diagonal memory variable:
+  velocity / stress        phi^aa (psi^aa) read + written                        ->  2 es
+  adj_velocity / adj_stress a psi~^aa (a phi~^aa) read, a phi~^aa (a psi~^aa) read + written -> 3 es
 Receivers: gather 24 + 8 + 8 bytes per (receiver, corner) plus 8 per trace
 sample; scatter the same per entry.
 """
@@ -27,6 +30,7 @@ from __future__ import annotations
 PER_CELL = {"velocity": 14, "stress": 17, "adj_velocity": 14, "adj_stress": 17}
 PER_PML_CELL = {"velocity": 6, "stress": 6, "adj_velocity": 9, "adj_stress": 9}
 PER_FLUID_CELL = {"velocity": 9, "stress": 8, "adj_velocity": 9, "adj_stress": 8}
+PER_FLUID_PML_CELL = {"velocity": 2, "stress": 2, "adj_velocity": 3, "adj_stress": 3}
 
 
 def pml_cells(nx: int, ny: int, nz: int, npml: int) -> int:
@@ -37,22 +41,25 @@ def pml_cells(nx: int, ny: int, nz: int, npml: int) -> int:
 
 
 def kernel_bytes(kind: str, nx: int, ny: int, nz: int, npml: int, nrec: int, es: int = 4,
-                 fluid_cells: int = 0) -> float:
+                 fluid_cells: int = 0, fluid_layer_cells: int = 0) -> float:
     """Algorithmic bytes of one launch of a kernel kind; fluid_cells of the volume take the
-    fluid-tile update (el_plan_fluid_path)."""
+    fluid-tile update, fluid_layer_cells of the C-PML (cell, axis) pairs lie in fluid tiles
+    (el_plan_fluid_path)."""
     N = nx * ny * nz
     if kind in PER_CELL:
+        layer = pml_cells(nx, ny, nz, npml)
         return float((N - fluid_cells) * PER_CELL[kind] * es + fluid_cells * PER_FLUID_CELL[kind] * es
-                     + pml_cells(nx, ny, nz, npml) * PER_PML_CELL[kind] * es)
+                     + (layer - fluid_layer_cells) * PER_PML_CELL[kind] * es
+                     + fluid_layer_cells * PER_FLUID_PML_CELL[kind] * es)
     if kind in ("gather", "scatter"):
         return float(nrec * 8 * (3 * es + 16) + nrec * 8)
     raise KeyError(kind)
 
 
-def step_bytes(op: str, nx, ny, nz, npml, nrec, es=4, fluid_cells: int = 0) -> float:
+def step_bytes(op: str, nx, ny, nz, npml, nrec, es=4, fluid_cells: int = 0, fluid_layer_cells: int = 0) -> float:
     """Bytes of one time step of the forward ('fwd') or adjoint ('adj') operator."""
     if op == "fwd":
         ks = ("velocity", "stress", "gather")
     else:
         ks = ("adj_velocity", "adj_stress", "scatter")
-    return sum(kernel_bytes(k, nx, ny, nz, npml, nrec, es, fluid_cells) for k in ks)
+    return sum(kernel_bytes(k, nx, ny, nz, npml, nrec, es, fluid_cells, fluid_layer_cells) for k in ks)

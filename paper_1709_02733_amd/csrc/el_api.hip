@@ -529,12 +529,24 @@ el_status el_plan_create(el_plan *out, const el_grid *grid, const float *lam, co
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         if (e != hipSuccess) return bail(hip_fail(e, "fluid tiles"));
         const Tiles &t = p->tiles;
+        const int P = grid->npml;
+        const int n[3] = {grid->nx, grid->ny, grid->nz};
+        // cells c of [c0, c1) in the layers of an axis of n cells (depth > 0: c < P or c > n-1-P)
+        auto in_layers = [P](int c0, int c1, int nn) {
+            if (P <= 0) return 0;
+            const int lo = std::max(0, std::min(c1, P) - c0);
+            const int hi = std::max(0, c1 - std::max(c0, nn - P));
+            return lo + hi;
+        };
         for (int q = 0; q < t.ntiles; ++q) {
             if (!p->fast[q]) continue;
             const int bx = q % t.ntx, r = q / t.ntx, by = r % t.nty, bz = r / t.nty;
+            const int c0[3] = {bx * kTileX, by * kTileY, bz * t.zc};
+            const int w[3] = {std::min(kTileX, n[0] - c0[0]), std::min(kTileY, n[1] - c0[1]), std::min(t.zc, n[2] - c0[2])};
             p->fast_tiles += 1;
-            p->fast_cells += (long long)(std::min(kTileX, grid->nx - bx * kTileX)) *
-                             std::min(kTileY, grid->ny - by * kTileY) * std::min(t.zc, grid->nz - bz * t.zc);
+            p->fast_cells += (long long)w[0] * w[1] * w[2];
+            for (int a = 0; a < 3; ++a)
+                p->fast_layer_cells += (long long)in_layers(c0[a], c0[a] + w[a], n[a]) * w[(a + 1) % 3] * w[(a + 2) % 3];
         }
         st = upload_order(p, s);
         if (st != EL_OK) return bail(st);
@@ -648,7 +660,8 @@ el_status el_plan_layout(el_plan p, int64_t *row_pitch, int64_t *plane_pitch, in
     return EL_OK;
 }
 
-el_status el_plan_fluid_path(el_plan p, int32_t enable, int64_t *fast_tiles, int64_t *fast_cells) {
+el_status el_plan_fluid_path(el_plan p, int32_t enable, int64_t *fast_tiles, int64_t *fast_cells,
+                             int64_t *fast_layer_cells) {
     el_status st = check_plan(p);
     if (st != EL_OK) return st;
     if (enable != -1 && enable != 0 && enable != 1) return fail(EL_EINVAL, "enable must be -1, 0 or 1");
@@ -660,6 +673,7 @@ el_status el_plan_fluid_path(el_plan p, int32_t enable, int64_t *fast_tiles, int
     }
     if (fast_tiles) *fast_tiles = p->fluid_path ? p->fast_tiles : 0;
     if (fast_cells) *fast_cells = p->fluid_path ? p->fast_cells : 0;
+    if (fast_layer_cells) *fast_layer_cells = p->fluid_path ? p->fast_layer_cells : 0;
     return EL_OK;
 }
 

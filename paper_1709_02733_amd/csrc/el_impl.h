@@ -197,6 +197,7 @@ struct el_plan_ {
     el::Tiles tiles;
     std::vector<unsigned char> fast;   // per tile: the fluid update applies (host copy)
     long long fast_tiles = 0, fast_cells = 0;
+    long long fast_layer_cells = 0;    // sum over axes of fluid-tile cells in that axis's C-PML layers
     bool fluid_path = true;            // use the fluid update where it applies
     hipEvent_t done;
     double cmax;

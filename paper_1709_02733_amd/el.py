@@ -80,7 +80,8 @@ def lib():
         L.el_plan_sizes.restype = st
         L.el_plan_sizes.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(i32), ctypes.POINTER(i32)]
         L.el_plan_fluid_path.restype = st
-        L.el_plan_fluid_path.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
+        L.el_plan_fluid_path.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
+                                         ctypes.POINTER(ctypes.c_int64)]
         L.el_plan_timing.restype = st
         L.el_plan_timing.argtypes = [vp, i32]
         L.el_plan_kernel_time.restype = st
@@ -234,10 +235,15 @@ class Plan:
     def fluid_path(self, enable: bool | None = None) -> tuple[int, int]:
         """Switch the fluid-tile update on or off (None keeps the setting); returns the number
         of tiles and of cells that take it (el_plan_fluid_path)."""
-        tiles, cells = ctypes.c_int64(0), ctypes.c_int64(0)
+        tiles, cells, layer = self.fluid_counts(enable)
+        return tiles, cells
+
+    def fluid_counts(self, enable: bool | None = None) -> tuple[int, int, int]:
+        """As fluid_path, plus the fluid cells in C-PML layers summed over the three axes."""
+        tiles, cells, layer = ctypes.c_int64(0), ctypes.c_int64(0), ctypes.c_int64(0)
         flag = -1 if enable is None else (1 if enable else 0)
-        _check(lib().el_plan_fluid_path(self._h, flag, ctypes.byref(tiles), ctypes.byref(cells)))
-        return tiles.value, cells.value
+        _check(lib().el_plan_fluid_path(self._h, flag, ctypes.byref(tiles), ctypes.byref(cells), ctypes.byref(layer)))
+        return tiles.value, cells.value, layer.value
 
     def timing(self, enable: bool = True):
         """Record an event pair around every time-loop kernel launch of later operations."""

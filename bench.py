@@ -27,7 +27,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Gcell-updates/s (fwd+adj) & % HBM roofline, 384^3; serving p50/p99 vs plain"
 HBM_PEAK_GBS = 8000.0
-KERNEL_SRCS = [os.path.join(ROOT, "paper_1709_02733_amd", "csrc", f) for f in ("el_stencil.hip", "el_impl.h")]
+KERNEL_SRCS = [os.path.join(ROOT, "paper_1709_02733_amd", "csrc", f) for f in ("el_stencil.hip", "el_impl.h", "el_api.hip")]
 TRAFFIC_JSON = os.path.join(ROOT, "profiles", "traffic.json")
 
 
@@ -36,8 +36,8 @@ def log(*a):
 
 
 def kernel_source_sha1() -> str:
-    """Hash of the stencil kernels' sources with comments and blank space removed (the
-    counters are valid for this version of the code only)."""
+    """Hash of the stencil kernels' sources and of their tiling (el_api.hip), with comments
+    and blank space removed: the counters are valid for this version of the code only."""
     h = hashlib.sha1()
     for fn in KERNEL_SRCS:
         with open(fn) as f:

@@ -156,6 +156,24 @@ el_status el_adjoint(el_plan plan, const double *y, void *p_adj, void *stream);
 el_status el_dot_f64(el_plan plan, int32_t space, const void *a, const void *b, double *out, void *stream);
 
 /*
+ * Transducer response.  The recorded signal is the pressure at the
+ * transducer convolved in time with the transducer's electrical impulse
+ * response (Sec. 2.3, the imaging model with the transducer's temporal
+ * response; the measured-data studies deconvolve it).  With one causal kernel
+ * h[0..nh-1] for every receiver, the operator E on traces [M][L] and its
+ * adjoint (a correlation) are
+ *   transpose 0:  out[m][l] = sum_{k=0}^{min(m, nh-1)}     h[k] in[m-k][l]
+ *   transpose 1:  out[m][l] = sum_{k=0}^{min(M-1-m, nh-1)} h[k] in[m+k][l]
+ * so E H is the imaging model with the response and H^T E^T its adjoint.
+ *   h (device): nh doubles.  in, out (device): nsteps * nrec doubles,
+ *   time-major, not overlapping.  No plan is needed.
+ * Asynchronous on `stream`.  Errors: EL_EINVAL for NULL pointers, nh < 1,
+ * nsteps < 1, nrec < 0, transpose outside 0..1, overlapping in/out.
+ */
+el_status el_eir_apply(const double *h, int32_t nh, const double *in, double *out, int32_t nsteps, int32_t nrec,
+                       int32_t transpose, void *stream);
+
+/*
  * Device pointer and element count of one of the plan's wavefield arrays,
  * for inspection after an operation has completed: id 0..2 = u1, u2, u3;
  * 3..8 = s11, s22, s33, s23, s13, s12 (elements of the plan's precision).

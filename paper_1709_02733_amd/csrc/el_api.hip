@@ -619,6 +619,21 @@ el_status el_adjoint(el_plan p, const double *y, void *p_adj, void *stream) {
     return EL_OK;
 }
 
+el_status el_eir_apply(const double *h, int32_t nh, const double *in, double *out, int32_t nsteps, int32_t nrec,
+                       int32_t transpose, void *stream) {
+    if (!h || !in || !out) return fail(EL_EINVAL, "h, in or out is NULL");
+    if (nh < 1) return fail(EL_EINVAL, "nh must be >= 1");
+    if (nsteps < 1 || nrec < 0) return fail(EL_EINVAL, "nsteps must be >= 1 and nrec >= 0");
+    if (transpose != 0 && transpose != 1) return fail(EL_EINVAL, "transpose must be 0 or 1");
+    const char *a0 = reinterpret_cast<const char *>(in), *b0 = reinterpret_cast<const char *>(out);
+    const size_t bytes = (size_t)nsteps * nrec * sizeof(double);
+    if (bytes > 0 && a0 < b0 + bytes && b0 < a0 + bytes) return fail(EL_EINVAL, "in and out overlap");
+    if ((size_t)nsteps * (size_t)nrec > (size_t)INT32_MAX * 64) return fail(EL_EINVAL, "traces too large");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    HIP_TRY(launch_eir(h, nh, in, out, nsteps, nrec, transpose, s), "transducer response");
+    return EL_OK;
+}
+
 el_status el_dot_f64(el_plan p, int32_t space, const void *a, const void *b, double *out, void *stream) {
     el_status st = check_plan(p);
     if (st != EL_OK) return st;

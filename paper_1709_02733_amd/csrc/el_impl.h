@@ -173,6 +173,8 @@ template <typename T> hipError_t launch_adj_velocity(const Dev<T> &d, const Tile
 template <typename T> hipError_t launch_adj_stress(const Dev<T> &d, const Tiles &tl, hipStream_t s);
 template <typename T> hipError_t launch_scatter(const Dev<T> &d, const Rec &r, const double *y_row, hipStream_t s);
 template <typename T> hipError_t launch_extract(const Dev<T> &d, T *p, hipStream_t s);
+hipError_t launch_eir(const double *h, int nh, const double *in, double *out, int M, int L, int transpose,
+                      hipStream_t s);
 template <typename T> hipError_t launch_dot(const T *a, const T *b, long long n, double *partial, double *out,
                                             hipStream_t s);
 hipError_t launch_set_counter(int *ctr, int v, hipStream_t s);

@@ -345,6 +345,36 @@ hipError_t launch_extract(const Dev<T> &d, T *p, hipStream_t s) {
     return hipGetLastError();
 }
 
+// ---------------------------------------------------- transducer response
+//
+// Every trace (time-major [M][L] doubles) convolved in time with one causal kernel
+// h[0..nh-1], or correlated with it (the adjoint).  One thread per output sample; the
+// lanes of a wavefront cover consecutive receivers, so every load is coalesced, and a
+// block's 64 consecutive time samples share the inputs of their window in L1.
+__global__ void k_eir(const double *h, int nh, const double *in, double *out, int M, int L, int transpose) {
+    const int nlb = (L + 63) / 64;
+    const int l = (int)(blockIdx.x % nlb) * 64 + (int)(threadIdx.x & 63);
+    const int m = (int)(blockIdx.x / nlb) * 4 + (int)(threadIdx.x >> 6);
+    if (l >= L || m >= M) return;
+    double acc = 0.0;
+    if (!transpose) {
+        const int kmax = min(m, nh - 1);
+        for (int k = 0; k <= kmax; ++k) acc += h[k] * in[(size_t)(m - k) * L + l];
+    } else {
+        const int kmax = min(M - 1 - m, nh - 1);
+        for (int k = 0; k <= kmax; ++k) acc += h[k] * in[(size_t)(m + k) * L + l];
+    }
+    out[(size_t)m * L + l] = acc;
+}
+
+hipError_t launch_eir(const double *h, int nh, const double *in, double *out, int M, int L, int transpose,
+                      hipStream_t s) {
+    if (M == 0 || L == 0) return hipSuccess;
+    const long long blocks = (long long)((L + 63) / 64) * ((M + 3) / 4);   // < 2^31 (checked by the caller)
+    hipLaunchKernelGGL(k_eir, dim3((unsigned)blocks), dim3(256), 0, s, h, nh, in, out, M, L, transpose);
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------ inner products
 
 template <typename T>

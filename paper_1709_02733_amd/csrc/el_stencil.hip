@@ -37,6 +37,12 @@
 // by tile_order on the host) that gives every XCD (block id mod 8) contiguous
 // regions of tiles spread over the volume, so every XCD holds the same share of
 // the C-PML layers and a region's neighbouring tiles share one L2.
+//
+// Fluid tiles (marked in the order table, see k_classify): where mu = 0 on the
+// tile and within two cells of it, s22 = s33 = s11 and the shear stresses are
+// zero on every tap, so both passes run a lean loop that differences s11
+// alone, writes the three normal stresses and carries only the diagonal
+// memory variables.  The results are those of the general loop.
 #include "el_impl.h"
 
 namespace el {

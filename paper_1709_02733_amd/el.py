@@ -38,7 +38,7 @@ class Grid(ctypes.Structure):
 
 _lib = None
 EXPORTS = ("el_version", "el_status_string", "el_last_error", "el_grid_check", "el_plan_bytes",
-           "el_plan_create", "el_plan_destroy", "el_forward", "el_adjoint", "el_dot_f64",
+           "el_plan_create", "el_plan_destroy", "el_forward", "el_adjoint", "el_dot_f64", "el_eir_apply",
            "el_plan_field", "el_plan_layout", "el_plan_sizes", "el_plan_fluid_path", "el_plan_timing",
            "el_plan_kernel_time",
            "el_exec_create", "el_exec_destroy", "el_exec_start", "el_exec_poll", "el_exec_wait", "el_exec_slots")
@@ -72,6 +72,8 @@ def lib():
         L.el_adjoint.argtypes = [vp, vp, vp, vp]
         L.el_dot_f64.restype = st
         L.el_dot_f64.argtypes = [vp, i32, vp, vp, vp, vp]
+        L.el_eir_apply.restype = st
+        L.el_eir_apply.argtypes = [vp, i32, vp, vp, i32, i32, i32, vp]
         L.el_plan_field.restype = st
         L.el_plan_field.argtypes = [vp, i32, ctypes.POINTER(vp), ctypes.POINTER(ctypes.c_size_t)]
         L.el_plan_layout.restype = st
@@ -272,6 +274,38 @@ class Plan:
         flat = self.workspace[off:off + cnt.value * es].view(self.dtype)
         nz, ny, nx = self.shape
         return flat.as_strided((nz, ny, nx), (pl.value, px.value, 1), flat.storage_offset() + org.value)
+
+
+def eir_apply(h: torch.Tensor, traces: torch.Tensor, transpose: bool = False, out=None, stream=None) -> torch.Tensor:
+    """Convolve every trace (float64 [M][L] on the device) in time with the causal kernel h
+    (el_eir_apply), or correlate with it when transpose is set (the adjoint)."""
+    if traces.dim() != 2 or traces.dtype != torch.float64 or not traces.is_cuda:
+        raise ValueError("traces must be a float64 [M][L] device tensor")
+    traces = traces.contiguous()
+    hd = h.to(device=traces.device, dtype=torch.float64).contiguous()
+    if out is None:
+        out = torch.empty_like(traces)
+    M, L = traces.shape
+    _check(lib().el_eir_apply(hd.data_ptr(), hd.numel(), traces.data_ptr(), out.data_ptr(), M, L,
+                              1 if transpose else 0, _stream(stream)))
+    return out
+
+
+class WithResponse:
+    """The imaging model with a transducer response: forward E H p, adjoint H^T E^T y
+    (E = el_eir_apply with kernel h).  Has the forward/adjoint/shape/dtype/device interface
+    of a Plan, so the reconstruction solvers accept it."""
+
+    def __init__(self, plan: "Plan", h: torch.Tensor):
+        self.plan = plan
+        self.h = h.to(device=plan.device, dtype=torch.float64).contiguous()
+        self.shape, self.dtype, self.device = plan.shape, plan.dtype, plan.device
+
+    def forward(self, p0):
+        return eir_apply(self.h, self.plan.forward(p0))
+
+    def adjoint(self, y):
+        return self.plan.adjoint(eir_apply(self.h, y.to(torch.float64), transpose=True))
 
 
 class Executor:

@@ -348,6 +348,17 @@ def random_scenario(shape_xyz=(12, 10, 9), seed: int = 0, nsteps: int = 20, npml
         p0=np.ascontiguousarray(p0, dtype=np.float32), rec=np.ascontiguousarray(rec * dx))
 
 
+def transducer_response(dt: float, f0: float = 2.25e6, cycles: float = 2.0) -> np.ndarray:
+    """Synthetic electrical impulse response of a transducer, sampled at dt: a sine at the
+    centre frequency f0 under a Gaussian window whose half-width is `cycles` periods,
+    causal (starting at t = 0), normalised to unit peak.  Stands in for a measured EIR."""
+    period = 1.0 / f0
+    t = np.arange(int(np.ceil(2 * cycles * period / dt)) + 1) * dt
+    tc = cycles * period
+    h = np.sin(2 * np.pi * f0 * (t - tc)) * np.exp(-0.5 * ((t - tc) / (0.5 * cycles * period)) ** 2)
+    return h / np.max(np.abs(h))
+
+
 def homogeneous_fluid_scenario(n: int, dx: float, nsteps: int, npml: int, p0: np.ndarray,
                                rec_cells: np.ndarray, cp: float = WATER_CP,
                                rho: float = WATER_RHO) -> Scenario:

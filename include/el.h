@@ -203,8 +203,13 @@ el_status el_plan_sizes(el_plan plan, int64_t *ncells, int32_t *nrec, int32_t *n
  * by a chunk of z planes) whose cells, and the cells within two of them,
  * all have mu = 0 is marked, and the stencil passes update such tiles from
  * the normal stress s11 alone, with only the diagonal C-PML memory
- * variables: fewer bytes, the same results (the shear stresses are not
- * written, s22 and s33 receive the value of s11).
+ * variables: fewer bytes, the same results.  The shear stresses are not
+ * written.  s22 and s33 equal s11 there; s22 is stored only on the two
+ * rows along a y face, and s33 only on the two planes along a z face, shared
+ * with a tile that takes the general update (whose taps read them there).
+ * The receiver gather takes 3 s11 as the trace of a cell in a fluid tile,
+ * and at the end of every operation one pass sets s22 = s33 = s11 on all
+ * fluid tiles, so el_plan_field shows the full state.
  *   enable: 1 use the fluid update where it applies (the default), 0 never,
  *           -1 keep the current setting.  A change waits for the plan's
  *           previous operation (host-blocking).
@@ -213,10 +218,12 @@ el_status el_plan_sizes(el_plan plan, int64_t *ncells, int32_t *nrec, int32_t *n
  *   *fast_layer_cells (host, may be NULL): the sum over the three axes of
  *           those cells that lie in the axis's C-PML layers (depth > 0); the
  *           fluid update carries only the diagonal memory variable there.
+ *   *skipped_stores (host, may be NULL): the s22 and s33 stores (cell,
+ *           component pairs) that one stress pass leaves out on fluid tiles.
  * Errors: EL_EINVAL for a NULL plan or an enable outside -1..1.
  */
 el_status el_plan_fluid_path(el_plan plan, int32_t enable, int64_t *fast_tiles, int64_t *fast_cells,
-                             int64_t *fast_layer_cells);
+                             int64_t *fast_layer_cells, int64_t *skipped_stores);
 
 /* Kernel kinds reported by el_plan_kernel_time(). */
 #define EL_K_VELOCITY     0   /* forward velocity pass (+ phi slabs)           */

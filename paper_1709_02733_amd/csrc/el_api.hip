@@ -88,6 +88,7 @@ bool layout(const el_grid &g, int nrec, Layout *L) {
     const size_t E = 8 * (size_t)std::max(nrec, 1);
     L->rec_idx = take(E * 8);
     L->rec_w = take(E * 8);
+    L->rec_fl = take(E);
     L->csr_pt = take(E * 8);
     L->csr_ptc = take(E * 3 * 4);
     L->csr_row = take((E + 1) * 4);
@@ -139,13 +140,26 @@ int tile_xcd(const Tiles &t, int q) {
     return (q / run) % 8;
 }
 
+int tile_edges(const Tiles &t, const unsigned char *fast, int q) {
+    if (!fast || !fast[q]) return 0;
+    const int b[2] = {(q / t.ntx) % t.nty, q / t.ntx / t.nty};
+    const int nb[2] = {t.nty, t.nzc};
+    const int step[2] = {t.ntx, t.ntx * t.nty};
+    int edges = 0;
+    for (int a = 0; a < 2; ++a) {   // y, z
+        if (b[a] > 0 && !fast[q - step[a]]) edges |= 1 << (kEdgeShift + 2 * a);
+        if (b[a] + 1 < nb[a] && !fast[q + step[a]]) edges |= 1 << (kEdgeShift + 2 * a + 1);
+    }
+    return edges;
+}
+
 std::vector<int> tile_order(const Tiles &t, const unsigned char *fast) {
     std::vector<int> order((size_t)8 * t.per, -1);
     std::vector<int> fill(8, 0);
     // tiles of an XCD in z-major order: a region's tiles are consecutive
     for (int q = 0; q < t.ntiles; ++q) {
         const int x = tile_xcd(t, q);
-        order[(size_t)fill[x]++ * 8 + x] = q | (fast && fast[q] ? kFastTile : 0);
+        order[(size_t)fill[x]++ * 8 + x] = q | (fast && fast[q] ? kFastTile | tile_edges(t, fast, q) : 0);
     }
     return order;
 }
@@ -190,6 +204,10 @@ el_status el_grid_check(const el_grid *g, const double *rec, int32_t nrec) {
         if (bytes >= (1LL << 32))
             return fail(EL_EINVAL, "grid %dx%dx%d: one padded volume array needs %lld bytes; the kernels address at most 4 GiB per array",
                         g->nx, g->ny, g->nz, bytes);
+        const long long tiles = (long long)((g->nx + kTileX - 1) / kTileX) * ((g->ny + kTileY - 1) / kTileY) *
+                                ((g->nz + kZChunk - 1) / kZChunk);
+        if (tiles > kTileMask)
+            return fail(EL_EINVAL, "grid %dx%dx%d: %lld stencil tiles, at most %d", g->nx, g->ny, g->nz, tiles, kTileMask);
     }
     if (nrec < 0) return fail(EL_EINVAL, "nrec must be >= 0");
     if (nrec > (1 << 26)) return fail(EL_EINVAL, "too many receivers");
@@ -311,6 +329,7 @@ el_status upload_receivers(el_plan_ *p, const double *rec, hipStream_t s) {
     std::vector<long long> idx(8 * (size_t)L);
     std::vector<int> cidx(3 * 8 * (size_t)L);
     std::vector<double> w(8 * (size_t)L);
+    p->rec_tile.assign(8 * (size_t)L, 0);
     for (int l = 0; l < L; ++l) {
         int b[3];
         double f[3];
@@ -328,6 +347,8 @@ el_status upload_receivers(el_plan_ *p, const double *rec, hipStream_t s) {
             cidx[3 * (8 * l + c) + 1] = b[1] + oy;
             cidx[3 * (8 * l + c) + 2] = b[2] + oz;
             w[8 * l + c] = (ox ? f[0] : 1 - f[0]) * (oy ? f[1] : 1 - f[1]) * (oz ? f[2] : 1 - f[2]);
+            const Tiles &t = p->tiles;
+            p->rec_tile[8 * l + c] = ((b[2] + oz) / t.zc * t.nty + (b[1] + oy) / kTileY) * t.ntx + (b[0] + ox) / kTileX;
         }
     }
     // grid-point-major transpose: entries sorted by (cell, receiver, corner)
@@ -353,6 +374,7 @@ el_status upload_receivers(el_plan_ *p, const double *rec, hipStream_t s) {
     r.nrec = L;
     r.idx = reinterpret_cast<long long *>(ws + p->L.rec_idx);
     r.w = reinterpret_cast<double *>(ws + p->L.rec_w);
+    r.fl = reinterpret_cast<unsigned char *>(ws + p->L.rec_fl);
     r.npts = (int)pt.size();
     r.pt = reinterpret_cast<long long *>(ws + p->L.csr_pt);
     r.ptc = reinterpret_cast<int *>(ws + p->L.csr_ptc);
@@ -373,11 +395,17 @@ el_status upload_receivers(el_plan_ *p, const double *rec, hipStream_t s) {
     return EL_OK;
 }
 
-// Upload the tile order table, with the fluid flags when the fluid update is enabled.
+// Upload the tile order table and the receiver corners' fluid flags, both with the fluid
+// tiles when the fluid update is enabled and without them otherwise.
 el_status upload_order(el_plan p, hipStream_t s) {
-    const std::vector<int> order = tile_order(p->tiles, p->fluid_path ? p->fast.data() : nullptr);
+    const unsigned char *fast = p->fluid_path ? p->fast.data() : nullptr;
+    const std::vector<int> order = tile_order(p->tiles, fast);
     int *dst = reinterpret_cast<int *>(p->ws + p->L.tile_order);
     HIP_TRY(hipMemcpyAsync(dst, order.data(), order.size() * sizeof(int), hipMemcpyHostToDevice, s), "tile order");
+    std::vector<unsigned char> fl(p->rec_tile.size(), 0);
+    for (size_t e = 0; e < fl.size(); ++e) fl[e] = fast && fast[p->rec_tile[e]] ? 1 : 0;
+    if (!fl.empty())
+        HIP_TRY(hipMemcpyAsync((void *)p->rec.fl, fl.data(), fl.size(), hipMemcpyHostToDevice, s), "receiver flags");
     HIP_TRY(hipStreamSynchronize(s), "tile order");
     p->tiles.order = dst;
     return EL_OK;
@@ -424,6 +452,7 @@ el_status run_forward(el_plan p, Dev<T> &d, const T *p0, double *traces, hipStre
         HIP_TRY(timed(p, EL_K_GATHER, s, [&] { return launch_gather(d, p->rec, traces + (size_t)m * L, s); }),
                 "gather");
     }
+    if (p->fluid_path && p->fast_tiles > 0) HIP_TRY(launch_fluid_fill(d, p->tiles, s), "fluid fill");
     return EL_OK;
 }
 
@@ -440,6 +469,7 @@ el_status run_adjoint(el_plan p, Dev<T> &d, const double *y, T *out, hipStream_t
         HIP_TRY(timed(p, EL_K_SCATTER, s, [&] { return launch_scatter(d, p->rec, y + (size_t)(m - 1) * L, s); }),
                 "scatter");
     }
+    if (p->fluid_path && p->fast_tiles > 0) HIP_TRY(launch_fluid_fill(d, p->tiles, s), "fluid fill");
     HIP_TRY(launch_extract(d, out, s), "extract");
     return EL_OK;
 }
@@ -545,6 +575,12 @@ el_status el_plan_create(el_plan *out, const el_grid *grid, const float *lam, co
             p->fast_cells += (long long)w[0] * w[1] * w[2];
             for (int a = 0; a < 3; ++a)
                 p->fast_layer_cells += (long long)in_layers(c0[a], c0[a] + w[a], n[a]) * w[(a + 1) % 3] * w[(a + 2) % 3];
+            // s22 (s33) is stored only on two-cell bands along y (z) faces next to general tiles
+            const int edges = tile_edges(t, p->fast.data(), q) >> kEdgeShift;
+            for (int a = 1; a < 3; ++a) {
+                const int lo = (edges >> (2 * (a - 1))) & 1, hi = (edges >> (2 * (a - 1) + 1)) & 1;
+                p->fast_skipped += (long long)std::max(0, w[a] - 2 * lo - 2 * hi) * w[(a + 1) % 3] * w[(a + 2) % 3];
+            }
         }
         st = upload_order(p, s);
         if (st != EL_OK) return bail(st);
@@ -674,7 +710,7 @@ el_status el_plan_layout(el_plan p, int64_t *row_pitch, int64_t *plane_pitch, in
 }
 
 el_status el_plan_fluid_path(el_plan p, int32_t enable, int64_t *fast_tiles, int64_t *fast_cells,
-                             int64_t *fast_layer_cells) {
+                             int64_t *fast_layer_cells, int64_t *skipped_stores) {
     el_status st = check_plan(p);
     if (st != EL_OK) return st;
     if (enable != -1 && enable != 0 && enable != 1) return fail(EL_EINVAL, "enable must be -1, 0 or 1");
@@ -687,6 +723,7 @@ el_status el_plan_fluid_path(el_plan p, int32_t enable, int64_t *fast_tiles, int
     if (fast_tiles) *fast_tiles = p->fluid_path ? p->fast_tiles : 0;
     if (fast_cells) *fast_cells = p->fluid_path ? p->fast_cells : 0;
     if (fast_layer_cells) *fast_layer_cells = p->fluid_path ? p->fast_layer_cells : 0;
+    if (skipped_stores) *skipped_stores = p->fluid_path ? p->fast_skipped : 0;
     return EL_OK;
 }
 

@@ -108,6 +108,7 @@ el_status start_op(el_exec ex, ExecSlot &sl, el_plan p, const Dev<T> &d, int op,
     }
     for (int c = 0; c < nfull; ++c) EX_TRY(hipGraphLaunch(sl.graph[0], s), "graph launch");
     if (rem > 0) EX_TRY(hipGraphLaunch(sl.graph[1], s), "graph launch");
+    if (p->fluid_path && p->fast_tiles > 0) EX_TRY(launch_fluid_fill(d, p->tiles, s), "fluid fill");
     if (op == EL_OP_ADJOINT) EX_TRY(launch_extract(d, static_cast<T *>(out), s), "extract");
     EX_TRY(hipEventRecord(p->done, s), "record plan completion");
     EX_TRY(hipEventRecord(sl.done, s), "record slot completion");

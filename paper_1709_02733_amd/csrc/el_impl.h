@@ -119,16 +119,26 @@ Tiles make_tiles(int nx, int ny, int nz);
 // XCD (0..7) that processes tile q; blocks run on XCD blockIdx % 8.
 int tile_xcd(const Tiles &t, int q);
 // Tile of each block (8 * per entries, -1 for padding blocks): the tiles of XCD x in z-major
-// order at entries x, x + 8, x + 16, ...  An entry carries kFastTile when fast[q] is set
-// (fast may be null): the block then runs the fluid update of the tile.
+// order at entries x, x + 8, x + 16, ...  An entry holds the tile number in its low
+// kEdgeShift bits and carries kFastTile when fast[q] is set (fast may be null): the block
+// then runs the fluid update of the tile.  The four bits from kEdgeShift up mark which face
+// neighbours of a fluid tile along y (y-, y+) and z (z-, z+) take the general update.  The
+// general loop differences s22 only along y and s33 only along z, with taps reaching two
+// cells into a neighbouring tile, so the fluid update stores s22 only on two-row bands
+// along such y faces and s33 only on two-plane bands along such z faces.
 constexpr int kFastTile = 1 << 30;
+constexpr int kEdgeShift = 24;
+constexpr int kTileMask = (1 << kEdgeShift) - 1;
 std::vector<int> tile_order(const Tiles &t, const unsigned char *fast);
+// Bits kEdgeShift.. of tile q's entry (0 unless q is a fluid tile).
+int tile_edges(const Tiles &t, const unsigned char *fast, int q);
 
 // Receiver tables (cell offsets are padded element indices).
 struct Rec {
     int nrec;
     const long long *idx;    // [L][8] corner elements
     const double *w;         // [L][8] trilinear weights
+    const unsigned char *fl; // [L][8] 1 where the corner lies in a fluid tile: trace is 3 s11
     // grid-point-major transpose for the deterministic scatter
     int npts;
     const long long *pt;     // [npts] touched elements
@@ -144,7 +154,7 @@ struct Layout {
     size_t map[4];           // lam, mu, rho, alpha
     size_t mem[3][6];
     size_t pa[3][2], pb[3][2];
-    size_t rec_idx, rec_w, csr_pt, csr_ptc, csr_row, csr_rec, csr_w;
+    size_t rec_idx, rec_w, rec_fl, csr_pt, csr_ptc, csr_row, csr_rec, csr_w;
     size_t stats;            // media statistics (16 doubles)
     size_t counter;          // device step counter of captured step graphs
     size_t tile_order;       // tile of each stencil block
@@ -173,6 +183,7 @@ template <typename T> hipError_t launch_adj_velocity(const Dev<T> &d, const Tile
 template <typename T> hipError_t launch_adj_stress(const Dev<T> &d, const Tiles &tl, hipStream_t s);
 template <typename T> hipError_t launch_scatter(const Dev<T> &d, const Rec &r, const double *y_row, hipStream_t s);
 template <typename T> hipError_t launch_extract(const Dev<T> &d, T *p, hipStream_t s);
+template <typename T> hipError_t launch_fluid_fill(const Dev<T> &d, const Tiles &tl, hipStream_t s);
 hipError_t launch_eir(const double *h, int nh, const double *in, double *out, int M, int L, int transpose,
                       hipStream_t s);
 template <typename T> hipError_t launch_dot(const T *a, const T *b, long long n, double *partial, double *out,
@@ -200,6 +211,8 @@ struct el_plan_ {
     std::vector<unsigned char> fast;   // per tile: the fluid update applies (host copy)
     long long fast_tiles = 0, fast_cells = 0;
     long long fast_layer_cells = 0;    // sum over axes of fluid-tile cells in that axis's C-PML layers
+    long long fast_skipped = 0;        // s22 and s33 stores a fluid stress pass leaves out
+    std::vector<int> rec_tile;         // [L][8] tile of each receiver corner (host)
     bool fluid_path = true;            // use the fluid update where it applies
     hipEvent_t done;
     double cmax;

@@ -41,8 +41,13 @@
 // Fluid tiles (marked in the order table, see k_classify): where mu = 0 on the
 // tile and within two cells of it, s22 = s33 = s11 and the shear stresses are
 // zero on every tap, so both passes run a lean loop that differences s11
-// alone, writes the three normal stresses and carries only the diagonal
-// memory variables.  The results are those of the general loop.
+// alone and carries only the diagonal memory variables.  s22 and s33 are read
+// only by the general loop, which differences s22 along y and s33 along z with
+// taps reaching two cells into a neighbouring tile, so the lean stress loop
+// stores s22 only on two-row bands along y faces shared with general tiles and
+// s33 only on two-plane bands along such z faces (edge bits of the order
+// entry), s11 everywhere; k_fluid_fill restores s22 = s33 = s11 on fluid tiles
+// at the end of an operation.  The results are those of the general loop.
 #include "el_impl.h"
 
 namespace el {
@@ -115,12 +120,15 @@ __device__ __forceinline__ T harmonic4r(T r0, T r1, T r2, T r3) {
 }
 
 // Tile of this block from the XCD-balanced order table; false for padding blocks.  fast is
-// set for a fluid tile (see k_classify).
-__device__ __forceinline__ bool tile_of(const Tiles &tl, int nz, int &x0, int &y0, int &z0, int &z1, bool &fast) {
+// set for a fluid tile (see k_classify), edges to its face neighbours that take the general
+// update (bits 0, 1: lower and upper side along y; bits 2, 3: along z).
+__device__ __forceinline__ bool tile_of(const Tiles &tl, int nz, int &x0, int &y0, int &z0, int &z1, bool &fast,
+                                        int &edges) {
     const int ent = tl.order[blockIdx.x];
     if (ent < 0) return false;
     fast = (ent & kFastTile) != 0;
-    const int t = ent & (kFastTile - 1);
+    edges = (ent >> kEdgeShift) & 15;
+    const int t = ent & kTileMask;
     const int bx = t % tl.ntx;
     const int r = t / tl.ntx;
     const int by = r % tl.nty;
@@ -145,9 +153,9 @@ __device__ __forceinline__ bool tile_of(const Tiles &tl, int nz, int &x0, int &y
 // ------------------------------------------------------------------------
 template <typename T, bool ADJ>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 5 : 1))) void k_vel(Dev<T> d, Tiles tl) {
-    int x0, y0, z0, z1;
+    int x0, y0, z0, z1, edges = 0;
     bool fast = false;
-    if (!tile_of(tl, d.nz, x0, y0, z0, z1, fast)) return;
+    if (!tile_of(tl, d.nz, x0, y0, z0, z1, fast, edges)) return;
     const int i = x0 + (int)threadIdx.x % TX, j = y0 + (int)threadIdx.x / TX;
     if (i >= d.nx || j >= d.ny) return;
     const T h = d.inv_dx, dt = d.dt;
@@ -368,9 +376,9 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
 // ------------------------------------------------------------------------
 template <typename T, bool ADJ>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 5 : 1))) void k_str(Dev<T> d, Tiles tl) {
-    int x0, y0, z0, z1;
+    int x0, y0, z0, z1, edges = 0;
     bool fast = false;
-    if (!tile_of(tl, d.nz, x0, y0, z0, z1, fast)) return;
+    if (!tile_of(tl, d.nz, x0, y0, z0, z1, fast, edges)) return;
     const int i = x0 + (int)threadIdx.x % TX, j = y0 + (int)threadIdx.x / TX;
     if (i >= d.nx || j >= d.ny) return;
     const T h = d.inv_dx, dt = d.dt;
@@ -384,6 +392,9 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
         // fluid tile: mu = 0, so the three normal stresses take the same increment lambda tr
         // and the shear stresses stay zero (not written).  Only the diagonal C-PML memory
         // variables (psi^{cc}; in the adjoint a phi~^{cc} and a psi~^{cc}) act on the trace.
+        // s22 is stored on the rows, s33 on the planes, that general tiles read across a face
+        const bool put22 = ((edges & 1) && j < y0 + 2) || ((edges & 2) && j >= y0 + TY - 2);
+        const int zlo = (edges & 4) ? z0 + 2 : z0, zhi = (edges & 8) ? z1 - 2 : z1;
         T qc[4];   // u3 at planes k-2..k+1
         qc[0] = T(0);
         qc[1] = ldb(u3, o - 2 * sz);
@@ -429,8 +440,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
             const T tr = e[0] + e[1] + e[2];
             const T w = sold + (ADJ ? T(-1) : dt) * (lam * tr);
             stb(d.f[S11], o, w);
-            stb(d.f[S22], o, w);
-            stb(d.f[S33], o, w);
+            if (put22) stb(d.f[S22], o, w);
+            if (k < zlo || k >= zhi) stb(d.f[S33], o, w);
             if (ADJ) {
 #pragma unroll
                 for (int a = 0; a < 3; ++a) {
@@ -595,7 +606,30 @@ hipError_t launch_adj_stress(const Dev<T> &d, const Tiles &tl, hipStream_t s) {
     return hipGetLastError();
 }
 
+// s22 = s33 = s11 on every fluid tile (the state the lean stress loop leaves implicit).
+template <typename T>
+__global__ __launch_bounds__(NT) void k_fluid_fill(Dev<T> d, Tiles tl) {
+    int x0, y0, z0, z1, edges = 0;
+    bool fast = false;
+    if (!tile_of(tl, d.nz, x0, y0, z0, z1, fast, edges) || !fast) return;
+    const int i = x0 + (int)threadIdx.x % TX, j = y0 + (int)threadIdx.x / TX;
+    if (i >= d.nx || j >= d.ny) return;
+    unsigned o = d.origin + (unsigned)z0 * d.sz + (unsigned)j * d.sy + (unsigned)i * (unsigned)sizeof(T);
+    for (int k = z0; k < z1; ++k, o += d.sz) {
+        const T v = ldb(d.f[S11], o);
+        stb(d.f[S22], o, v);
+        stb(d.f[S33], o, v);
+    }
+}
+
+template <typename T>
+hipError_t launch_fluid_fill(const Dev<T> &d, const Tiles &tl, hipStream_t s) {
+    hipLaunchKernelGGL(k_fluid_fill<T>, dim3(8 * tl.per), dim3(NT), 0, s, d, tl);
+    return hipGetLastError();
+}
+
 #define EL_STENCIL_INST(T)                                                                  \
+    template hipError_t launch_fluid_fill<T>(const Dev<T> &, const Tiles &, hipStream_t);   \
     template hipError_t launch_velocity<T>(const Dev<T> &, const Tiles &, hipStream_t);     \
     template hipError_t launch_stress<T>(const Dev<T> &, const Tiles &, hipStream_t);       \
     template hipError_t launch_adj_velocity<T>(const Dev<T> &, const Tiles &, hipStream_t); \

@@ -83,7 +83,7 @@ def lib():
         L.el_plan_sizes.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(i32), ctypes.POINTER(i32)]
         L.el_plan_fluid_path.restype = st
         L.el_plan_fluid_path.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
-                                         ctypes.POINTER(ctypes.c_int64)]
+                                         ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
         L.el_plan_timing.restype = st
         L.el_plan_timing.argtypes = [vp, i32]
         L.el_plan_kernel_time.restype = st
@@ -237,15 +237,16 @@ class Plan:
     def fluid_path(self, enable: bool | None = None) -> tuple[int, int]:
         """Switch the fluid-tile update on or off (None keeps the setting); returns the number
         of tiles and of cells that take it (el_plan_fluid_path)."""
-        tiles, cells, layer = self.fluid_counts(enable)
+        tiles, cells, _, _ = self.fluid_counts(enable)
         return tiles, cells
 
-    def fluid_counts(self, enable: bool | None = None) -> tuple[int, int, int]:
-        """As fluid_path, plus the fluid cells in C-PML layers summed over the three axes."""
-        tiles, cells, layer = ctypes.c_int64(0), ctypes.c_int64(0), ctypes.c_int64(0)
+    def fluid_counts(self, enable: bool | None = None) -> tuple[int, int, int, int]:
+        """As fluid_path, plus the fluid cells in C-PML layers summed over the three axes and
+        the s22 / s33 stores one stress pass leaves out on fluid tiles."""
+        out = [ctypes.c_int64(0) for _ in range(4)]
         flag = -1 if enable is None else (1 if enable else 0)
-        _check(lib().el_plan_fluid_path(self._h, flag, ctypes.byref(tiles), ctypes.byref(cells), ctypes.byref(layer)))
-        return tiles.value, cells.value, layer.value
+        _check(lib().el_plan_fluid_path(self._h, flag, *(ctypes.byref(v) for v in out)))
+        return tuple(v.value for v in out)
 
     def timing(self, enable: bool = True):
         """Record an event pair around every time-loop kernel launch of later operations."""

@@ -164,21 +164,35 @@ def test_fluid_tiles_match_general_update_and_oracle(precision, tol_same, tol_re
     Sec. 2.1): H and H^T equal the general update and the oracle."""
     sc = _fluid_ball_scenario()
     plan = el.Plan.from_scenario(sc, precision=precision)
-    tiles, cells = plan.fluid_path()
-    banner(f"fluid tiles {tiles}, cells {cells} of {sc.ncells}")
+    tiles, cells, _, skipped = plan.fluid_counts()
+    banner(f"fluid tiles {tiles}, cells {cells} of {sc.ncells}, s22/s33 stores left out {skipped}")
     assert tiles > 0 and 0 < cells < sc.ncells
+    # the ball's neighbourhood leaves y and z faces next to general tiles: both bands occur
+    assert 0 < skipped < 2 * cells
     p = torch.from_numpy(sc.p0)
     y = np.random.default_rng(3).standard_normal((sc.nsteps, sc.nrec))
-    tr_fast = plan.forward(p).cpu().numpy()
-    pa_fast = plan.adjoint(torch.from_numpy(y)).cpu().numpy().astype(np.float64)
-    assert plan.fluid_path(False) == (0, 0)
-    tr_gen = plan.forward(p).cpu().numpy()
-    pa_gen = plan.adjoint(torch.from_numpy(y)).cpu().numpy().astype(np.float64)
-    assert plan.fluid_path(True) == (tiles, cells)
+
+    def run():
+        tr = plan.forward(p).cpu().numpy()
+        fwd_state = {f: plan.field(f).cpu().numpy().astype(np.float64) for f in el.FIELDS}
+        pa = plan.adjoint(torch.from_numpy(y)).cpu().numpy().astype(np.float64)
+        adj_state = {f: plan.field(f).cpu().numpy().astype(np.float64) for f in el.FIELDS}
+        return tr, pa, fwd_state, adj_state
+
+    tr_fast, pa_fast, fs_fast, as_fast = run()
+    assert plan.fluid_counts(False) == (0, 0, 0, 0)
+    tr_gen, pa_gen, fs_gen, as_gen = run()
+    assert plan.fluid_counts(True) == (tiles, cells, plan.fluid_counts()[2], skipped)
     banner(f"fluid vs general: traces bitwise {np.array_equal(tr_fast, tr_gen)}, "
            f"max {rel_max(tr_fast, tr_gen):.2e}; adjoint bitwise {np.array_equal(pa_fast, pa_gen)}, "
            f"max {rel_max(pa_fast, pa_gen):.2e}")
     assert rel_max(tr_fast, tr_gen) <= tol_same and rel_max(pa_fast, pa_gen) <= tol_same
+    # the whole state after each operation (s22 = s33 = s11 restored on fluid tiles)
+    for name in el.FIELDS:
+        for a, b, op in ((fs_fast, fs_gen, "forward"), (as_fast, as_gen, "adjoint")):
+            scale = max(np.abs(b[name]).max(), np.abs(b["s11"]).max())
+            err = np.abs(a[name] - b[name]).max() / scale
+            assert err <= tol_same, (op, name, err)
     ref = Model.from_scenario(sc)
     assert rel_l2(tr_fast, ref.forward(sc.p0.astype(np.float64))) <= tol_ref
     assert rel_l2(pa_fast, ref.adjoint(y)) <= tol_ref

@@ -142,9 +142,12 @@ def main():
     log(f"[bench] workload {sc.name}: {sc.nx}x{sc.ny}x{sc.nz}, M={sc.nsteps}, L={sc.nrec}, npml={sc.npml}, "
         f"dt={sc.dt:.4e}s, generated in {time.time() - t0:.1f}s")
     plan = el.Plan.from_scenario(sc)
-    fluid_tiles, fluid_cells, fluid_layer, skipped = plan.fluid_counts()
-    log(f"[bench] fluid tiles: {fluid_tiles} ({fluid_cells / sc.ncells:.1%} of the cells take the fluid update; "
-        f"{fluid_layer} fluid C-PML cell-axis pairs; {skipped} s22/s33 stores left out per stress pass)")
+    fl = plan.fluid_stats()
+    fluid_cells, fluid_layer = fl["cells"], fl["layer_cells"]
+    skipped, uniform = fl["skipped_stores"], fl["uniform_cells"]
+    log(f"[bench] fluid tiles: {fl['tiles']} ({fluid_cells / sc.ncells:.1%} of the cells take the fluid update; "
+        f"{fluid_layer} fluid C-PML cell-axis pairs; {skipped} s22/s33 stores left out per stress pass; "
+        f"{uniform / sc.ncells:.1%} of the cells in uniform fluid tiles)")
     dev = plan.device
     p0 = torch.from_numpy(sc.p0).to(dev)
     traces = torch.empty((sc.nsteps, sc.nrec), dtype=torch.float64, device=dev)
@@ -186,7 +189,7 @@ def main():
         if n == 0:
             continue
         b = bytemodel.kernel_bytes(name, sc.nx, sc.ny, sc.nz, sc.npml, sc.nrec, 4, fluid_cells, fluid_layer,
-                                   skipped)
+                                   skipped, uniform)
         avg = ms / n
         per[name] = dict(launches=n, total_ms=ms, avg_us=avg * 1e3, bytes_per_launch=b,
                          gbs=b / (avg / 1e3) / 1e9)
@@ -198,7 +201,7 @@ def main():
                 "frac": d["gbs"] / HBM_PEAK_GBS, "traffic": traffic, "kernel": dom,
                 "bytes_per_launch": d["bytes_per_launch"], "avg_launch_us": d["avg_us"]}
     step_gb = sum(bytemodel.step_bytes(op, sc.nx, sc.ny, sc.nz, sc.npml, sc.nrec, 4, fluid_cells, fluid_layer,
-                                       skipped) for op in ("fwd", "adj")) * (sc.nsteps - 1)
+                                       skipped, uniform) for op in ("fwd", "adj")) * (sc.nsteps - 1)
     whole_gbs = step_gb * args.steps / (total_ms / 1e3) / 1e9
 
     serving = None
@@ -239,7 +242,8 @@ def main():
                                f"forward H + adjoint H^T per step",
                    "nx": sc.nx, "ny": sc.ny, "nz": sc.nz, "nsteps": sc.nsteps, "npml": sc.npml,
                    "nrec": sc.nrec, "seed": sc.seed, "fluid_tile_cells": fluid_cells,
-                   "fluid_layer_cells": fluid_layer, "fluid_skipped_stores": skipped},
+                   "fluid_layer_cells": fluid_layer, "fluid_skipped_stores": skipped,
+                   "fluid_uniform_cells": uniform},
         "fwd_gcells": upd * args.steps / (fwd_ms / 1e3) / 1e9,
         "adj_gcells": upd * args.steps / (adj_ms / 1e3) / 1e9,
         "whole_step_gbs": whole_gbs,

@@ -209,21 +209,32 @@ el_status el_plan_sizes(el_plan plan, int64_t *ncells, int32_t *nrec, int32_t *n
  * with a tile that takes the general update (whose taps read them there).
  * The receiver gather takes 3 s11 as the trace of a cell in a fluid tile,
  * and at the end of every operation one pass sets s22 = s33 = s11 on all
- * fluid tiles, so el_plan_field shows the full state.
+ * fluid tiles, so el_plan_field shows the full state.  A fluid tile whose
+ * lambda, rho and alpha are each one value over that box (a homogeneous
+ * coupling medium such as the water of Sec. 7) takes the three values from
+ * a per-tile table instead of the maps, again with the same results.
+ */
+typedef struct el_fluid_stats {
+    int64_t tiles;           /* tiles that take the fluid update                   */
+    int64_t cells;           /* their cells                                        */
+    int64_t layer_cells;     /* sum over the three axes of those cells in the      */
+                             /* axis's C-PML layers (depth > 0): only the diagonal */
+                             /* memory variable is carried there                   */
+    int64_t skipped_stores;  /* s22 and s33 stores (cell, component pairs) one     */
+                             /* stress pass leaves out                             */
+    int64_t uniform_cells;   /* cells of fluid tiles with uniform lambda, rho,     */
+                             /* alpha (maps not read)                              */
+} el_fluid_stats;
+
+/*
  *   enable: 1 use the fluid update where it applies (the default), 0 never,
  *           -1 keep the current setting.  A change waits for the plan's
  *           previous operation (host-blocking).
- *   *fast_tiles, *fast_cells (host, may be NULL): tiles and cells that take
- *           the fluid update under the resulting setting.
- *   *fast_layer_cells (host, may be NULL): the sum over the three axes of
- *           those cells that lie in the axis's C-PML layers (depth > 0); the
- *           fluid update carries only the diagonal memory variable there.
- *   *skipped_stores (host, may be NULL): the s22 and s33 stores (cell,
- *           component pairs) that one stress pass leaves out on fluid tiles.
+ *   *stats (host, may be NULL): the counts under the resulting setting (all
+ *           zero when the fluid update is off).
  * Errors: EL_EINVAL for a NULL plan or an enable outside -1..1.
  */
-el_status el_plan_fluid_path(el_plan plan, int32_t enable, int64_t *fast_tiles, int64_t *fast_cells,
-                             int64_t *fast_layer_cells, int64_t *skipped_stores);
+el_status el_plan_fluid_path(el_plan plan, int32_t enable, el_fluid_stats *stats);
 
 /* Kernel kinds reported by el_plan_kernel_time(). */
 #define EL_K_VELOCITY     0   /* forward velocity pass (+ phi slabs)           */

@@ -21,6 +21,8 @@ s22 = s33 = s11 and the shear stresses are zero:
   stress / adj_stress      reads u x3, s11, lambda;     writes s11, s22, s33      ->  8 es
 less one element for every s22 or s33 store the stress passes leave out (those
 stresses are stored only where a general-update tile reads them, el_plan_fluid_path),
+less rho and alpha (velocity) or lambda (stress) on a fluid tile of uniform media, whose
+values come from a per-tile table,
 and per fluid cell of each axis's C-PML layers only the diagonal memory variable:
   velocity / stress        phi^aa (psi^aa) read + written                        ->  2 es
   adj_velocity / adj_stress a psi~^aa (a phi~^aa) read, a phi~^aa (a psi~^aa) read + written -> 3 es
@@ -33,6 +35,8 @@ PER_CELL = {"velocity": 14, "stress": 17, "adj_velocity": 14, "adj_stress": 17}
 PER_PML_CELL = {"velocity": 6, "stress": 6, "adj_velocity": 9, "adj_stress": 9}
 PER_FLUID_CELL = {"velocity": 9, "stress": 8, "adj_velocity": 9, "adj_stress": 8}
 PER_FLUID_PML_CELL = {"velocity": 2, "stress": 2, "adj_velocity": 3, "adj_stress": 3}
+UNIFORM_MAPS_VELOCITY = 2   # rho, alpha
+UNIFORM_MAPS_STRESS = 1     # lambda
 
 
 def pml_cells(nx: int, ny: int, nz: int, npml: int) -> int:
@@ -43,16 +47,20 @@ def pml_cells(nx: int, ny: int, nz: int, npml: int) -> int:
 
 
 def kernel_bytes(kind: str, nx: int, ny: int, nz: int, npml: int, nrec: int, es: int = 4,
-                 fluid_cells: int = 0, fluid_layer_cells: int = 0, skipped_stores: int = 0) -> float:
+                 fluid_cells: int = 0, fluid_layer_cells: int = 0, skipped_stores: int = 0,
+                 uniform_cells: int = 0) -> float:
     """Algorithmic bytes of one launch of a kernel kind; fluid_cells of the volume take the
     fluid-tile update, fluid_layer_cells of the C-PML (cell, axis) pairs lie in fluid tiles,
-    and the stress passes leave out skipped_stores s22 / s33 stores (el_plan_fluid_path)."""
+    the stress passes leave out skipped_stores s22 / s33 stores, and uniform_cells of the
+    fluid cells read no material map (el_plan_fluid_path)."""
     N = nx * ny * nz
     if kind in PER_CELL:
         layer = pml_cells(nx, ny, nz, npml)
-        skipped = skipped_stores if kind in ("stress", "adj_stress") else 0
+        stress = kind in ("stress", "adj_stress")
+        skipped = skipped_stores if stress else 0
+        maps = uniform_cells * (UNIFORM_MAPS_STRESS if stress else UNIFORM_MAPS_VELOCITY)
         return float((N - fluid_cells) * PER_CELL[kind] * es + fluid_cells * PER_FLUID_CELL[kind] * es
-                     - skipped * es
+                     - skipped * es - maps * es
                      + (layer - fluid_layer_cells) * PER_PML_CELL[kind] * es
                      + fluid_layer_cells * PER_FLUID_PML_CELL[kind] * es)
     if kind in ("gather", "scatter"):
@@ -61,11 +69,11 @@ def kernel_bytes(kind: str, nx: int, ny: int, nz: int, npml: int, nrec: int, es:
 
 
 def step_bytes(op: str, nx, ny, nz, npml, nrec, es=4, fluid_cells: int = 0, fluid_layer_cells: int = 0,
-               skipped_stores: int = 0) -> float:
+               skipped_stores: int = 0, uniform_cells: int = 0) -> float:
     """Bytes of one time step of the forward ('fwd') or adjoint ('adj') operator."""
     if op == "fwd":
         ks = ("velocity", "stress", "gather")
     else:
         ks = ("adj_velocity", "adj_stress", "scatter")
-    return sum(kernel_bytes(k, nx, ny, nz, npml, nrec, es, fluid_cells, fluid_layer_cells, skipped_stores)
-               for k in ks)
+    return sum(kernel_bytes(k, nx, ny, nz, npml, nrec, es, fluid_cells, fluid_layer_cells, skipped_stores,
+                            uniform_cells) for k in ks)

@@ -99,7 +99,8 @@ bool layout(const el_grid &g, int nrec, Layout *L) {
     {
         const Tiles t = make_tiles(g.nx, g.ny, g.nz);
         L->tile_order = take((size_t)8 * t.per * sizeof(int));
-        L->tile_flags = take((size_t)t.ntiles);
+        L->tile_flags = take(2 * (size_t)t.ntiles);
+        L->tile_media = take((size_t)4 * t.ntiles * es);
     }
     L->partial = take(7 * kDotBlocks * 8);
     L->total = off;
@@ -153,13 +154,15 @@ int tile_edges(const Tiles &t, const unsigned char *fast, int q) {
     return edges;
 }
 
-std::vector<int> tile_order(const Tiles &t, const unsigned char *fast) {
+std::vector<int> tile_order(const Tiles &t, const unsigned char *fast, const unsigned char *uni) {
     std::vector<int> order((size_t)8 * t.per, -1);
     std::vector<int> fill(8, 0);
     // tiles of an XCD in z-major order: a region's tiles are consecutive
     for (int q = 0; q < t.ntiles; ++q) {
         const int x = tile_xcd(t, q);
-        order[(size_t)fill[x]++ * 8 + x] = q | (fast && fast[q] ? kFastTile | tile_edges(t, fast, q) : 0);
+        const bool f = fast && fast[q];
+        order[(size_t)fill[x]++ * 8 + x] =
+            q | (f ? kFastTile | tile_edges(t, fast, q) | (uni && uni[q] ? kUniformTile : 0) : 0);
     }
     return order;
 }
@@ -283,6 +286,7 @@ void bind(Dev<T> &d, el_plan_ *p) {
     d.mu = reinterpret_cast<T *>(ws + p->L.map[1]);
     d.rho = reinterpret_cast<T *>(ws + p->L.map[2]);
     d.alpha = reinterpret_cast<T *>(ws + p->L.map[3]);
+    d.med = reinterpret_cast<T *>(ws + p->L.tile_media);
     d.P = g.npml;
     const int n[3] = {g.nx, g.ny, g.nz};
     for (int a = 0; a < 3; ++a) d.hi[a] = n[a] - 1 - g.npml;
@@ -399,7 +403,7 @@ el_status upload_receivers(el_plan_ *p, const double *rec, hipStream_t s) {
 // tiles when the fluid update is enabled and without them otherwise.
 el_status upload_order(el_plan p, hipStream_t s) {
     const unsigned char *fast = p->fluid_path ? p->fast.data() : nullptr;
-    const std::vector<int> order = tile_order(p->tiles, fast);
+    const std::vector<int> order = tile_order(p->tiles, fast, p->uni.data());
     int *dst = reinterpret_cast<int *>(p->ws + p->L.tile_order);
     HIP_TRY(hipMemcpyAsync(dst, order.data(), order.size() * sizeof(int), hipMemcpyHostToDevice, s), "tile order");
     std::vector<unsigned char> fl(p->rec_tile.size(), 0);
@@ -549,11 +553,16 @@ el_status el_plan_create(el_plan *out, const el_grid *grid, const float *lam, co
     {
         // fluid tiles (el_kernels.hip, k_classify), then the order table
         unsigned char *flags = reinterpret_cast<unsigned char *>(p->ws + L.tile_flags);
-        e = grid->precision == EL_F64 ? launch_classify(p->dd, p->tiles, flags, s)
-                                      : launch_classify(p->df, p->tiles, flags, s);
+        unsigned char *uflags = flags + p->tiles.ntiles;
+        e = grid->precision == EL_F64
+                ? launch_classify(p->dd, p->tiles, flags, uflags, const_cast<double *>(p->dd.med), s)
+                : launch_classify(p->df, p->tiles, flags, uflags, const_cast<float *>(p->df.med), s);
         p->fast.assign(p->tiles.ntiles, 0);
+        p->uni.assign(p->tiles.ntiles, 0);
         if (e == hipSuccess && p->tiles.ntiles > 0)
             e = hipMemcpyAsync(p->fast.data(), flags, p->fast.size(), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess && p->tiles.ntiles > 0)
+            e = hipMemcpyAsync(p->uni.data(), uflags, p->uni.size(), hipMemcpyDeviceToHost, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         if (e != hipSuccess) return bail(hip_fail(e, "fluid tiles"));
         const Tiles &t = p->tiles;
@@ -573,6 +582,7 @@ el_status el_plan_create(el_plan *out, const el_grid *grid, const float *lam, co
             const int w[3] = {std::min(kTileX, n[0] - c0[0]), std::min(kTileY, n[1] - c0[1]), std::min(t.zc, n[2] - c0[2])};
             p->fast_tiles += 1;
             p->fast_cells += (long long)w[0] * w[1] * w[2];
+            if (p->uni[q]) p->uniform_cells += (long long)w[0] * w[1] * w[2];
             for (int a = 0; a < 3; ++a)
                 p->fast_layer_cells += (long long)in_layers(c0[a], c0[a] + w[a], n[a]) * w[(a + 1) % 3] * w[(a + 2) % 3];
             // s22 (s33) is stored only on two-cell bands along y (z) faces next to general tiles
@@ -709,8 +719,7 @@ el_status el_plan_layout(el_plan p, int64_t *row_pitch, int64_t *plane_pitch, in
     return EL_OK;
 }
 
-el_status el_plan_fluid_path(el_plan p, int32_t enable, int64_t *fast_tiles, int64_t *fast_cells,
-                             int64_t *fast_layer_cells, int64_t *skipped_stores) {
+el_status el_plan_fluid_path(el_plan p, int32_t enable, el_fluid_stats *stats) {
     el_status st = check_plan(p);
     if (st != EL_OK) return st;
     if (enable != -1 && enable != 0 && enable != 1) return fail(EL_EINVAL, "enable must be -1, 0 or 1");
@@ -720,10 +729,16 @@ el_status el_plan_fluid_path(el_plan p, int32_t enable, int64_t *fast_tiles, int
         st = upload_order(p, nullptr);
         if (st != EL_OK) return st;
     }
-    if (fast_tiles) *fast_tiles = p->fluid_path ? p->fast_tiles : 0;
-    if (fast_cells) *fast_cells = p->fluid_path ? p->fast_cells : 0;
-    if (fast_layer_cells) *fast_layer_cells = p->fluid_path ? p->fast_layer_cells : 0;
-    if (skipped_stores) *skipped_stores = p->fluid_path ? p->fast_skipped : 0;
+    if (stats) {
+        *stats = el_fluid_stats{};
+        if (p->fluid_path) {
+            stats->tiles = p->fast_tiles;
+            stats->cells = p->fast_cells;
+            stats->layer_cells = p->fast_layer_cells;
+            stats->skipped_stores = p->fast_skipped;
+            stats->uniform_cells = p->uniform_cells;
+        }
+    }
     return EL_OK;
 }
 

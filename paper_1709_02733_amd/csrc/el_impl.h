@@ -61,6 +61,7 @@ struct Dev {
     T *mem[3][6];            // boundary-slab memory variables of axis j:
                              //   mem[j][i]     = phi^{ij} (u^i point),
                              //   mem[j][3 + i] = psi^{ij} (sigma^{ij} point)
+    const T *med;            // per tile: lambda, rho, alpha, 0 of a uniform fluid tile
 };
 
 // Boundary-slab storage of the C-PML memory variables.  Along each axis the variables live on
@@ -126,10 +127,13 @@ int tile_xcd(const Tiles &t, int q);
 // general loop differences s22 only along y and s33 only along z, with taps reaching two
 // cells into a neighbouring tile, so the fluid update stores s22 only on two-row bands
 // along such y faces and s33 only on two-plane bands along such z faces.
+// kUniformTile marks a fluid tile whose lambda, rho and alpha are constant over the cells
+// its loops read (k_classify): they come from a per-tile table instead of the maps.
 constexpr int kFastTile = 1 << 30;
+constexpr int kUniformTile = 1 << 29;
 constexpr int kEdgeShift = 24;
 constexpr int kTileMask = (1 << kEdgeShift) - 1;
-std::vector<int> tile_order(const Tiles &t, const unsigned char *fast);
+std::vector<int> tile_order(const Tiles &t, const unsigned char *fast, const unsigned char *uni);
 // Bits kEdgeShift.. of tile q's entry (0 unless q is a fluid tile).
 int tile_edges(const Tiles &t, const unsigned char *fast, int q);
 
@@ -158,7 +162,8 @@ struct Layout {
     size_t stats;            // media statistics (16 doubles)
     size_t counter;          // device step counter of captured step graphs
     size_t tile_order;       // tile of each stencil block
-    size_t tile_flags;       // per tile: 1 if the fluid update applies
+    size_t tile_flags;       // per tile: 1 if the fluid update applies; then per tile: 1 if uniform
+    size_t tile_media;       // per tile: lambda, rho, alpha, 0 (elements of the plan's precision)
     size_t partial;          // reduction partials
     size_t total;
 };
@@ -174,7 +179,7 @@ hipError_t launch_media_stats(const float *lam, const float *mu, const float *rh
                               long long n, double dt, double *stats, double *partial, hipStream_t s);
 template <typename T> hipError_t launch_zero_state(const Dev<T> &d, hipStream_t s);
 template <typename T> hipError_t launch_classify(const Dev<T> &d, const Tiles &tl, unsigned char *fast,
-                                                 hipStream_t s);
+                                                 unsigned char *uni, T *med, hipStream_t s);
 template <typename T> hipError_t launch_inject(const Dev<T> &d, const T *p0, hipStream_t s);
 template <typename T> hipError_t launch_velocity(const Dev<T> &d, const Tiles &tl, hipStream_t s);
 template <typename T> hipError_t launch_stress(const Dev<T> &d, const Tiles &tl, hipStream_t s);
@@ -209,6 +214,8 @@ struct el_plan_ {
     el::Rec rec;
     el::Tiles tiles;
     std::vector<unsigned char> fast;   // per tile: the fluid update applies (host copy)
+    std::vector<unsigned char> uni;    // per tile: fluid with uniform lambda, rho, alpha (host copy)
+    long long uniform_cells = 0;       // cells of uniform fluid tiles
     long long fast_tiles = 0, fast_cells = 0;
     long long fast_layer_cells = 0;    // sum over axes of fluid-tile cells in that axis's C-PML layers
     long long fast_skipped = 0;        // s22 and s33 stores a fluid stress pass leaves out

@@ -140,33 +140,63 @@ hipError_t launch_zero_state(const Dev<T> &d, hipStream_t s) {
 // alone, with only the diagonal C-PML memory variables (a solid cell is at least three
 // cells from the tile, out of reach of its taps).  One block per tile checks mu over that
 // box; cells outside the grid count as fluid (zero extension).
+//
+// A fluid tile whose lambda, rho and alpha are each one value (bit for bit) over the same
+// box is also marked uniform, and its three values are written to med[4 q + 0..2]: the
+// stencil passes then take them from there instead of reading the maps (the box holds every
+// map cell the fluid loops read, the edge-replicated padding included), with the same
+// arithmetic and so the same results.
 template <typename T>
-__global__ void k_classify(Dev<T> d, Tiles tl, unsigned char *fast) {
+__device__ __forceinline__ bool same_bits(T a, T b);
+template <>
+__device__ __forceinline__ bool same_bits<float>(float a, float b) {
+    return __float_as_uint(a) == __float_as_uint(b);
+}
+template <>
+__device__ __forceinline__ bool same_bits<double>(double a, double b) {
+    return __double_as_longlong(a) == __double_as_longlong(b);
+}
+
+template <typename T>
+__global__ void k_classify(Dev<T> d, Tiles tl, unsigned char *fast, unsigned char *uni, T *med) {
     const int q = blockIdx.x;
     if (q >= tl.ntiles) return;
     const int bx = q % tl.ntx, r = q / tl.ntx, by = r % tl.nty, bz = r / tl.nty;
     const int x0 = bx * kTileX, y0 = by * kTileY, z0 = bz * tl.zc;
     const int x1 = min(x0 + kTileX, d.nx), y1 = min(y0 + kTileY, d.ny), z1 = min(z0 + tl.zc, d.nz);
-    int solid = 0;
+    int solid = 0, vary = 0;
+    const int ax = max(x0 - 2, 0), ay = max(y0 - 2, 0), az = max(z0 - 2, 0);
+    const long long e0 = (long long)(az + 2) * d.plane + (long long)ay * d.px + ax;
+    const T l0 = d.lam[e0], r0 = d.rho[e0], a0 = d.alpha[e0];
     {
-        const int ax = max(x0 - 2, 0), ay = max(y0 - 2, 0), az = max(z0 - 2, 0);
         const int w = min(x1 + 2, d.nx) - ax, hgt = min(y1 + 2, d.ny) - ay, dep = min(z1 + 2, d.nz) - az;
         const long long n = (long long)w * hgt * dep;
         for (long long e = threadIdx.x; e < n; e += blockDim.x) {
             const int xx = ax + (int)(e % w);
             const long long rr = e / w;
             const int yy = ay + (int)(rr % hgt), zz = az + (int)(rr / hgt);
-            if (d.mu[(long long)(zz + 2) * d.plane + (long long)yy * d.px + xx] != T(0)) solid = 1;
+            const long long c = (long long)(zz + 2) * d.plane + (long long)yy * d.px + xx;
+            if (d.mu[c] != T(0)) solid = 1;
+            if (!same_bits(d.lam[c], l0) || !same_bits(d.rho[c], r0) || !same_bits(d.alpha[c], a0)) vary = 1;
         }
     }
     solid = __syncthreads_or(solid);
-    if (threadIdx.x == 0) fast[q] = solid ? 0 : 1;
+    vary = __syncthreads_or(vary);
+    if (threadIdx.x == 0) {
+        fast[q] = solid ? 0 : 1;
+        uni[q] = solid || vary ? 0 : 1;
+        med[4 * (size_t)q + 0] = l0;
+        med[4 * (size_t)q + 1] = r0;
+        med[4 * (size_t)q + 2] = a0;
+        med[4 * (size_t)q + 3] = T(0);
+    }
 }
 
 template <typename T>
-hipError_t launch_classify(const Dev<T> &d, const Tiles &tl, unsigned char *fast, hipStream_t s) {
+hipError_t launch_classify(const Dev<T> &d, const Tiles &tl, unsigned char *fast, unsigned char *uni, T *med,
+                           hipStream_t s) {
     if (tl.ntiles == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_classify<T>, dim3(tl.ntiles), dim3(256), 0, s, d, tl, fast);
+    hipLaunchKernelGGL(k_classify<T>, dim3(tl.ntiles), dim3(256), 0, s, d, tl, fast, uni, med);
     return hipGetLastError();
 }
 
@@ -423,7 +453,8 @@ hipError_t launch_dot(const T *a, const T *b, long long n, double *partial, doub
     template hipError_t launch_convert_maps<T>(const Dev<T> &, const float *, const float *, const float *,          \
                                                const float *, hipStream_t);                                          \
     template hipError_t launch_zero_state<T>(const Dev<T> &, hipStream_t);                                           \
-    template hipError_t launch_classify<T>(const Dev<T> &, const Tiles &, unsigned char *, hipStream_t);             \
+    template hipError_t launch_classify<T>(const Dev<T> &, const Tiles &, unsigned char *, unsigned char *, T *,     \
+                                           hipStream_t);                                                             \
     template hipError_t launch_inject<T>(const Dev<T> &, const T *, hipStream_t);                                    \
     template hipError_t launch_gather<T>(const Dev<T> &, const Rec &, double *, hipStream_t);                        \
     template hipError_t launch_scatter<T>(const Dev<T> &, const Rec &, const double *, hipStream_t);                 \

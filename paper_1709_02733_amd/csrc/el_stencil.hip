@@ -119,16 +119,18 @@ __device__ __forceinline__ T harmonic4r(T r0, T r1, T r2, T r3) {
     return T(4) * rcp(r0 + r1 + r2 + r3);
 }
 
-// Tile of this block from the XCD-balanced order table; false for padding blocks.  fast is
-// set for a fluid tile (see k_classify), edges to its face neighbours that take the general
-// update (bits 0, 1: lower and upper side along y; bits 2, 3: along z).
-__device__ __forceinline__ bool tile_of(const Tiles &tl, int nz, int &x0, int &y0, int &z0, int &z1, bool &fast,
-                                        int &edges) {
+// Tile t of this block from the XCD-balanced order table; false for padding blocks.  fast is
+// set for a fluid tile (see k_classify), uni for a fluid tile of uniform media, edges to its
+// face neighbours that take the general update (bits 0, 1: lower and upper side along y;
+// bits 2, 3: along z).
+__device__ __forceinline__ bool tile_of(const Tiles &tl, int nz, int &x0, int &y0, int &z0, int &z1, int &t,
+                                        bool &fast, bool &uni, int &edges) {
     const int ent = tl.order[blockIdx.x];
     if (ent < 0) return false;
     fast = (ent & kFastTile) != 0;
+    uni = (ent & kUniformTile) != 0;
     edges = (ent >> kEdgeShift) & 15;
-    const int t = ent & kTileMask;
+    t = ent & kTileMask;
     const int bx = t % tl.ntx;
     const int r = t / tl.ntx;
     const int by = r % tl.nty;
@@ -151,11 +153,102 @@ __device__ __forceinline__ bool tile_of(const Tiles &tl, int nz, int &x0, int &y
 //   axis y: c=0 s12 (Dm), c=1 s22 (Dp), c=2 s23 (Dm)
 //   axis z: c=0 s13 (Dm), c=1 s23 (Dm), c=2 s33 (Dp)
 // ------------------------------------------------------------------------
+// Fluid-tile loop of the velocity-shaped pass.  UNI: a uniform tile, whose rho and alpha
+// come from the per-tile table instead of the maps (the same values, so the same results).
+template <typename T, bool ADJ, bool UNI>
+__device__ __forceinline__ void fluid_vel(const Dev<T> &d, int i, int j, int z0, int z1, unsigned o, int t,
+                                          int snx, int sny, int sox, int soy) {
+    const T h = d.inv_dx, dt = d.dt;
+    const unsigned sx = sizeof(T), sy = d.sy, sz = d.sz;
+    const T *s11 = d.f[S11];
+    const bool pml = d.P > 0;
+    // fluid tile: s22 = s33 = s11 and the shear stresses are zero on every tap, so the
+    // three nonzero differences are those of s11 along x, y and z.  Of the C-PML memory
+    // variables only the diagonal ones (phi^{cc}; in the adjoint a psi~^{cc} and
+    // a phi~^{cc}) act on fluid cells: the others stay zero or meet only zero moduli.
+    T qs[4];   // s11 at planes k-1..k+2
+    qs[0] = T(0);
+    qs[1] = ldb(s11, o - sz);
+    qs[2] = ldb(s11, o);
+    qs[3] = ldb(s11, o + sz);
+    const T rho_t = UNI ? d.med[4 * t + 1] : T(0), alp_t = UNI ? d.med[4 * t + 2] : T(0);
+    T rho_k = UNI ? rho_t : ldb(d.rho, o), alp_k = UNI ? alp_t : ldb(d.alpha, o);
+    for (int k = z0; k < z1; ++k, o += sz) {
+#pragma unroll
+        for (int n = 0; n < 3; ++n) qs[n] = qs[n + 1];
+        qs[3] = ldb(s11, o + 2 * sz);
+        T a11[4], b11[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            a11[q] = ldb(s11, o + (unsigned)(q - 1) * sx);
+            b11[q] = ldb(s11, o + (unsigned)(q - 1) * sy);
+        }
+        T uold[3], rho_n[3], alp_n[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) uold[c] = ldb(d.f[U1 + c], o);
+        rho_n[0] = UNI ? rho_t : ldb(d.rho, o + sx);
+        rho_n[1] = UNI ? rho_t : ldb(d.rho, o + sy);
+        rho_n[2] = UNI ? rho_t : ldb(d.rho, o + sz);
+        alp_n[0] = UNI ? alp_t : ldb(d.alpha, o + sx);
+        alp_n[1] = UNI ? alp_t : ldb(d.alpha, o + sy);
+        alp_n[2] = UNI ? alp_t : ldb(d.alpha, o + sz);
+        __builtin_amdgcn_sched_barrier(0);
+        T acc[3];
+        acc[0] = dplus(a11[0], a11[1], a11[2], a11[3], h);
+        acc[1] = dplus(b11[0], b11[1], b11[2], b11[3], h);
+        acc[2] = dplus(qs[0], qs[1], qs[2], qs[3], h);
+        const int crd[3] = {i, j, k};
+        const int slab[3] = {sox, soy, pml ? slab_own(k, d.P, d.hi[2]) : -1};
+        if (ADJ) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) acc[c] *= dt;
+            const int near[3] = {snx, sny, pml ? slab_near(k, d.P, d.hi[2]) : -1};
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+                if (near[a] >= 0)
+                    acc[a] += dp_at(d.mem[a][3 + a], slab_byte(d, a, near[a], i, j, k), slab_stride(d, a), h);
+        } else {
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                if (slab[a] < 0) continue;
+                const unsigned q = slab_byte(d, a, slab[a], i, j, k);
+                const T phi = d.pb[a][1][crd[a]] * ldb(d.mem[a][a], q) + d.pa[a][1][crd[a]] * acc[a];
+                stb(d.mem[a][a], q, phi);
+                acc[a] += phi;
+            }
+        }
+        T out[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const T rho_c = T(0.5) * (rho_k + rho_n[c]);
+            const T alp_c = T(0.5) * (alp_k + alp_n[c]);
+            const T irho = rcp(rho_c);
+            out[c] = ADJ ? (T(1) - dt * alp_c) * uold[c] - acc[c] * irho
+                         : (T(1) - dt * alp_c) * uold[c] + dt * irho * acc[c];
+            stb(d.f[U1 + c], o, out[c]);
+        }
+        rho_k = rho_n[2];
+        alp_k = alp_n[2];
+        if (ADJ) {
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                if (slab[a] < 0) continue;
+                // g' = a phi~^{aa} <- b g' + a dt r^a
+                const unsigned q = slab_byte(d, a, slab[a], i, j, k);
+                const int tw = slab_twin(crd[a], d.P, d.hi[a]);
+                const T g = d.pb[a][1][crd[a]] * ldb(d.mem[a][a], q) + d.pa[a][1][crd[a]] * dt * out[a];
+                stb(d.mem[a][a], q, g);
+                if (tw >= 0) stb(d.mem[a][a], slab_byte(d, a, tw, i, j, k), g);
+            }
+        }
+    }
+}
+
 template <typename T, bool ADJ>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 5 : 1))) void k_vel(Dev<T> d, Tiles tl) {
-    int x0, y0, z0, z1, edges = 0;
-    bool fast = false;
-    if (!tile_of(tl, d.nz, x0, y0, z0, z1, fast, edges)) return;
+    int x0, y0, z0, z1, t = 0, edges = 0;
+    bool fast = false, uni = false;
+    if (!tile_of(tl, d.nz, x0, y0, z0, z1, t, fast, uni, edges)) return;
     const int i = x0 + (int)threadIdx.x % TX, j = y0 + (int)threadIdx.x / TX;
     if (i >= d.nx || j >= d.ny) return;
     const T h = d.inv_dx, dt = d.dt;
@@ -166,85 +259,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
     const int snx = pml ? slab_near(i, d.P, d.hi[0]) : -1, sny = pml ? slab_near(j, d.P, d.hi[1]) : -1;
     const int sox = pml ? slab_own(i, d.P, d.hi[0]) : -1, soy = pml ? slab_own(j, d.P, d.hi[1]) : -1;
     if (fast) {
-        // fluid tile: s22 = s33 = s11 and the shear stresses are zero on every tap, so the
-        // three nonzero differences are those of s11 along x, y and z.  Of the C-PML memory
-        // variables only the diagonal ones (phi^{cc}; in the adjoint a psi~^{cc} and
-        // a phi~^{cc}) act on fluid cells: the others stay zero or meet only zero moduli.
-        T qs[4];   // s11 at planes k-1..k+2
-        qs[0] = T(0);
-        qs[1] = ldb(s11, o - sz);
-        qs[2] = ldb(s11, o);
-        qs[3] = ldb(s11, o + sz);
-        T rho_k = ldb(d.rho, o), alp_k = ldb(d.alpha, o);
-        for (int k = z0; k < z1; ++k, o += sz) {
-#pragma unroll
-            for (int n = 0; n < 3; ++n) qs[n] = qs[n + 1];
-            qs[3] = ldb(s11, o + 2 * sz);
-            T a11[4], b11[4];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                a11[q] = ldb(s11, o + (unsigned)(q - 1) * sx);
-                b11[q] = ldb(s11, o + (unsigned)(q - 1) * sy);
-            }
-            T uold[3], rho_n[3], alp_n[3];
-#pragma unroll
-            for (int c = 0; c < 3; ++c) uold[c] = ldb(d.f[U1 + c], o);
-            rho_n[0] = ldb(d.rho, o + sx);
-            rho_n[1] = ldb(d.rho, o + sy);
-            rho_n[2] = ldb(d.rho, o + sz);
-            alp_n[0] = ldb(d.alpha, o + sx);
-            alp_n[1] = ldb(d.alpha, o + sy);
-            alp_n[2] = ldb(d.alpha, o + sz);
-            __builtin_amdgcn_sched_barrier(0);
-            T acc[3];
-            acc[0] = dplus(a11[0], a11[1], a11[2], a11[3], h);
-            acc[1] = dplus(b11[0], b11[1], b11[2], b11[3], h);
-            acc[2] = dplus(qs[0], qs[1], qs[2], qs[3], h);
-            const int crd[3] = {i, j, k};
-            const int slab[3] = {sox, soy, pml ? slab_own(k, d.P, d.hi[2]) : -1};
-            if (ADJ) {
-#pragma unroll
-                for (int c = 0; c < 3; ++c) acc[c] *= dt;
-                const int near[3] = {snx, sny, pml ? slab_near(k, d.P, d.hi[2]) : -1};
-#pragma unroll
-                for (int a = 0; a < 3; ++a)
-                    if (near[a] >= 0)
-                        acc[a] += dp_at(d.mem[a][3 + a], slab_byte(d, a, near[a], i, j, k), slab_stride(d, a), h);
-            } else {
-#pragma unroll
-                for (int a = 0; a < 3; ++a) {
-                    if (slab[a] < 0) continue;
-                    const unsigned q = slab_byte(d, a, slab[a], i, j, k);
-                    const T phi = d.pb[a][1][crd[a]] * ldb(d.mem[a][a], q) + d.pa[a][1][crd[a]] * acc[a];
-                    stb(d.mem[a][a], q, phi);
-                    acc[a] += phi;
-                }
-            }
-            T out[3];
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                const T rho_c = T(0.5) * (rho_k + rho_n[c]);
-                const T alp_c = T(0.5) * (alp_k + alp_n[c]);
-                const T irho = rcp(rho_c);
-                out[c] = ADJ ? (T(1) - dt * alp_c) * uold[c] - acc[c] * irho
-                             : (T(1) - dt * alp_c) * uold[c] + dt * irho * acc[c];
-                stb(d.f[U1 + c], o, out[c]);
-            }
-            rho_k = rho_n[2];
-            alp_k = alp_n[2];
-            if (ADJ) {
-#pragma unroll
-                for (int a = 0; a < 3; ++a) {
-                    if (slab[a] < 0) continue;
-                    // g' = a phi~^{aa} <- b g' + a dt r^a
-                    const unsigned q = slab_byte(d, a, slab[a], i, j, k);
-                    const int tw = slab_twin(crd[a], d.P, d.hi[a]);
-                    const T g = d.pb[a][1][crd[a]] * ldb(d.mem[a][a], q) + d.pa[a][1][crd[a]] * dt * out[a];
-                    stb(d.mem[a][a], q, g);
-                    if (tw >= 0) stb(d.mem[a][a], slab_byte(d, a, tw, i, j, k), g);
-                }
-            }
-        }
+        if (uni) fluid_vel<T, ADJ, true>(d, i, j, z0, z1, o, t, snx, sny, sox, soy);
+        else fluid_vel<T, ADJ, false>(d, i, j, z0, z1, o, t, snx, sny, sox, soy);
         return;
     }
     T qa[4], qb[4], qc[4];   // s13, s23 at planes k-2..k+1; s33 at planes k-1..k+2
@@ -374,11 +390,89 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
 // stress-shaped pass.  In_ca lives in field u^c (forward) or r^c (adjoint):
 //   axis x: c=0 Dm, c=1 Dp, c=2 Dp;  axis y: c=0 Dp, c=1 Dm, c=2 Dp;  axis z: c=0 Dp, c=1 Dp, c=2 Dm
 // ------------------------------------------------------------------------
+// Fluid-tile loop of the stress-shaped pass.  UNI: a uniform tile, whose lambda comes from
+// the per-tile table instead of the map (the same value, so the same results).
+template <typename T, bool ADJ, bool UNI>
+__device__ __forceinline__ void fluid_str(const Dev<T> &d, int i, int j, int y0, int z0, int z1, unsigned o,
+                                          int t, int edges, int snx, int sny, int sox, int soy) {
+    const T h = d.inv_dx, dt = d.dt;
+    const unsigned sx = sizeof(T), sy = d.sy, sz = d.sz;
+    const T *u1 = d.f[U1], *u2 = d.f[U2], *u3 = d.f[U3];
+    const bool pml = d.P > 0;
+    const T lam_t = UNI ? d.med[4 * t] : T(0);
+    // fluid tile: mu = 0, so the three normal stresses take the same increment lambda tr
+    // and the shear stresses stay zero (not written).  Only the diagonal C-PML memory
+    // variables (psi^{cc}; in the adjoint a phi~^{cc} and a psi~^{cc}) act on the trace.
+    // s22 is stored on the rows, s33 on the planes, that general tiles read across a face
+    const bool put22 = ((edges & 1) && j < y0 + 2) || ((edges & 2) && j >= y0 + TY - 2);
+    const int zlo = (edges & 4) ? z0 + 2 : z0, zhi = (edges & 8) ? z1 - 2 : z1;
+    T qc[4];   // u3 at planes k-2..k+1
+    qc[0] = T(0);
+    qc[1] = ldb(u3, o - 2 * sz);
+    qc[2] = ldb(u3, o - sz);
+    qc[3] = ldb(u3, o);
+    for (int k = z0; k < z1; ++k, o += sz) {
+#pragma unroll
+        for (int n = 0; n < 3; ++n) qc[n] = qc[n + 1];
+        qc[3] = ldb(u3, o + sz);
+        T a1[4], b2[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            a1[q] = ldb(u1, o + (unsigned)(q - 2) * sx);
+            b2[q] = ldb(u2, o + (unsigned)(q - 2) * sy);
+        }
+        const T sold = ldb(d.f[S11], o);
+        const T lam = UNI ? lam_t : ldb(d.lam, o);
+        __builtin_amdgcn_sched_barrier(0);
+        T e[3];
+        e[0] = dminus(a1[0], a1[1], a1[2], a1[3], h);
+        e[1] = dminus(b2[0], b2[1], b2[2], b2[3], h);
+        e[2] = dminus(qc[0], qc[1], qc[2], qc[3], h);
+        const int crd[3] = {i, j, k};
+        const int slab[3] = {sox, soy, pml ? slab_own(k, d.P, d.hi[2]) : -1};
+        if (ADJ) {
+#pragma unroll
+            for (int a = 0; a < 3; ++a) e[a] *= dt;
+            const int near[3] = {snx, sny, pml ? slab_near(k, d.P, d.hi[2]) : -1};
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+                if (near[a] >= 0)
+                    e[a] += dm_at(d.mem[a][a], slab_byte(d, a, near[a], i, j, k), slab_stride(d, a), h);
+        } else {
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                if (slab[a] < 0) continue;
+                const unsigned q = slab_byte(d, a, slab[a], i, j, k);
+                const T psi = d.pb[a][0][crd[a]] * ldb(d.mem[a][3 + a], q) + d.pa[a][0][crd[a]] * e[a];
+                stb(d.mem[a][3 + a], q, psi);
+                e[a] += psi;
+            }
+        }
+        const T tr = e[0] + e[1] + e[2];
+        const T w = sold + (ADJ ? T(-1) : dt) * (lam * tr);
+        stb(d.f[S11], o, w);
+        if (put22) stb(d.f[S22], o, w);
+        if (k < zlo || k >= zhi) stb(d.f[S33], o, w);
+        if (ADJ) {
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                if (slab[a] < 0) continue;
+                // g = a psi~^{aa} <- b g + a dt w_aa
+                const unsigned q = slab_byte(d, a, slab[a], i, j, k);
+                const int tw = slab_twin(crd[a], d.P, d.hi[a]);
+                const T g = d.pb[a][0][crd[a]] * ldb(d.mem[a][3 + a], q) + d.pa[a][0][crd[a]] * dt * w;
+                stb(d.mem[a][3 + a], q, g);
+                if (tw >= 0) stb(d.mem[a][3 + a], slab_byte(d, a, tw, i, j, k), g);
+            }
+        }
+    }
+}
+
 template <typename T, bool ADJ>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 5 : 1))) void k_str(Dev<T> d, Tiles tl) {
-    int x0, y0, z0, z1, edges = 0;
-    bool fast = false;
-    if (!tile_of(tl, d.nz, x0, y0, z0, z1, fast, edges)) return;
+    int x0, y0, z0, z1, t = 0, edges = 0;
+    bool fast = false, uni = false;
+    if (!tile_of(tl, d.nz, x0, y0, z0, z1, t, fast, uni, edges)) return;
     const int i = x0 + (int)threadIdx.x % TX, j = y0 + (int)threadIdx.x / TX;
     if (i >= d.nx || j >= d.ny) return;
     const T h = d.inv_dx, dt = d.dt;
@@ -389,72 +483,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
     const int snx = pml ? slab_near(i, d.P, d.hi[0]) : -1, sny = pml ? slab_near(j, d.P, d.hi[1]) : -1;
     const int sox = pml ? slab_own(i, d.P, d.hi[0]) : -1, soy = pml ? slab_own(j, d.P, d.hi[1]) : -1;
     if (fast) {
-        // fluid tile: mu = 0, so the three normal stresses take the same increment lambda tr
-        // and the shear stresses stay zero (not written).  Only the diagonal C-PML memory
-        // variables (psi^{cc}; in the adjoint a phi~^{cc} and a psi~^{cc}) act on the trace.
-        // s22 is stored on the rows, s33 on the planes, that general tiles read across a face
-        const bool put22 = ((edges & 1) && j < y0 + 2) || ((edges & 2) && j >= y0 + TY - 2);
-        const int zlo = (edges & 4) ? z0 + 2 : z0, zhi = (edges & 8) ? z1 - 2 : z1;
-        T qc[4];   // u3 at planes k-2..k+1
-        qc[0] = T(0);
-        qc[1] = ldb(u3, o - 2 * sz);
-        qc[2] = ldb(u3, o - sz);
-        qc[3] = ldb(u3, o);
-        for (int k = z0; k < z1; ++k, o += sz) {
-#pragma unroll
-            for (int n = 0; n < 3; ++n) qc[n] = qc[n + 1];
-            qc[3] = ldb(u3, o + sz);
-            T a1[4], b2[4];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                a1[q] = ldb(u1, o + (unsigned)(q - 2) * sx);
-                b2[q] = ldb(u2, o + (unsigned)(q - 2) * sy);
-            }
-            const T sold = ldb(d.f[S11], o);
-            const T lam = ldb(d.lam, o);
-            __builtin_amdgcn_sched_barrier(0);
-            T e[3];
-            e[0] = dminus(a1[0], a1[1], a1[2], a1[3], h);
-            e[1] = dminus(b2[0], b2[1], b2[2], b2[3], h);
-            e[2] = dminus(qc[0], qc[1], qc[2], qc[3], h);
-            const int crd[3] = {i, j, k};
-            const int slab[3] = {sox, soy, pml ? slab_own(k, d.P, d.hi[2]) : -1};
-            if (ADJ) {
-#pragma unroll
-                for (int a = 0; a < 3; ++a) e[a] *= dt;
-                const int near[3] = {snx, sny, pml ? slab_near(k, d.P, d.hi[2]) : -1};
-#pragma unroll
-                for (int a = 0; a < 3; ++a)
-                    if (near[a] >= 0)
-                        e[a] += dm_at(d.mem[a][a], slab_byte(d, a, near[a], i, j, k), slab_stride(d, a), h);
-            } else {
-#pragma unroll
-                for (int a = 0; a < 3; ++a) {
-                    if (slab[a] < 0) continue;
-                    const unsigned q = slab_byte(d, a, slab[a], i, j, k);
-                    const T psi = d.pb[a][0][crd[a]] * ldb(d.mem[a][3 + a], q) + d.pa[a][0][crd[a]] * e[a];
-                    stb(d.mem[a][3 + a], q, psi);
-                    e[a] += psi;
-                }
-            }
-            const T tr = e[0] + e[1] + e[2];
-            const T w = sold + (ADJ ? T(-1) : dt) * (lam * tr);
-            stb(d.f[S11], o, w);
-            if (put22) stb(d.f[S22], o, w);
-            if (k < zlo || k >= zhi) stb(d.f[S33], o, w);
-            if (ADJ) {
-#pragma unroll
-                for (int a = 0; a < 3; ++a) {
-                    if (slab[a] < 0) continue;
-                    // g = a psi~^{aa} <- b g + a dt w_aa
-                    const unsigned q = slab_byte(d, a, slab[a], i, j, k);
-                    const int tw = slab_twin(crd[a], d.P, d.hi[a]);
-                    const T g = d.pb[a][0][crd[a]] * ldb(d.mem[a][3 + a], q) + d.pa[a][0][crd[a]] * dt * w;
-                    stb(d.mem[a][3 + a], q, g);
-                    if (tw >= 0) stb(d.mem[a][3 + a], slab_byte(d, a, tw, i, j, k), g);
-                }
-            }
-        }
+        if (uni) fluid_str<T, ADJ, true>(d, i, j, y0, z0, z1, o, t, edges, snx, sny, sox, soy);
+        else fluid_str<T, ADJ, false>(d, i, j, y0, z0, z1, o, t, edges, snx, sny, sox, soy);
         return;
     }
     T qa[4], qb[4], qc[4];   // u1, u2 at planes k-1..k+2; u3 at planes k-2..k+1
@@ -609,9 +639,9 @@ hipError_t launch_adj_stress(const Dev<T> &d, const Tiles &tl, hipStream_t s) {
 // s22 = s33 = s11 on every fluid tile (the state the lean stress loop leaves implicit).
 template <typename T>
 __global__ __launch_bounds__(NT) void k_fluid_fill(Dev<T> d, Tiles tl) {
-    int x0, y0, z0, z1, edges = 0;
-    bool fast = false;
-    if (!tile_of(tl, d.nz, x0, y0, z0, z1, fast, edges) || !fast) return;
+    int x0, y0, z0, z1, t = 0, edges = 0;
+    bool fast = false, uni = false;
+    if (!tile_of(tl, d.nz, x0, y0, z0, z1, t, fast, uni, edges) || !fast) return;
     const int i = x0 + (int)threadIdx.x % TX, j = y0 + (int)threadIdx.x / TX;
     if (i >= d.nx || j >= d.ny) return;
     unsigned o = d.origin + (unsigned)z0 * d.sz + (unsigned)j * d.sy + (unsigned)i * (unsigned)sizeof(T);

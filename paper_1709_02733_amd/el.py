@@ -36,6 +36,12 @@ class Grid(ctypes.Structure):
                 ("precision", ctypes.c_int32)]
 
 
+class FluidStats(ctypes.Structure):
+    """el_fluid_stats (include/el.h)."""
+    _fields_ = [("tiles", ctypes.c_int64), ("cells", ctypes.c_int64), ("layer_cells", ctypes.c_int64),
+                ("skipped_stores", ctypes.c_int64), ("uniform_cells", ctypes.c_int64)]
+
+
 _lib = None
 EXPORTS = ("el_version", "el_status_string", "el_last_error", "el_grid_check", "el_plan_bytes",
            "el_plan_create", "el_plan_destroy", "el_forward", "el_adjoint", "el_dot_f64", "el_eir_apply",
@@ -82,8 +88,7 @@ def lib():
         L.el_plan_sizes.restype = st
         L.el_plan_sizes.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(i32), ctypes.POINTER(i32)]
         L.el_plan_fluid_path.restype = st
-        L.el_plan_fluid_path.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
-                                         ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
+        L.el_plan_fluid_path.argtypes = [vp, i32, ctypes.POINTER(FluidStats)]
         L.el_plan_timing.restype = st
         L.el_plan_timing.argtypes = [vp, i32]
         L.el_plan_kernel_time.restype = st
@@ -237,16 +242,18 @@ class Plan:
     def fluid_path(self, enable: bool | None = None) -> tuple[int, int]:
         """Switch the fluid-tile update on or off (None keeps the setting); returns the number
         of tiles and of cells that take it (el_plan_fluid_path)."""
-        tiles, cells, _, _ = self.fluid_counts(enable)
-        return tiles, cells
+        st = self.fluid_stats(enable)
+        return st["tiles"], st["cells"]
 
-    def fluid_counts(self, enable: bool | None = None) -> tuple[int, int, int, int]:
-        """As fluid_path, plus the fluid cells in C-PML layers summed over the three axes and
-        the s22 / s33 stores one stress pass leaves out on fluid tiles."""
-        out = [ctypes.c_int64(0) for _ in range(4)]
+    def fluid_stats(self, enable: bool | None = None) -> dict:
+        """As fluid_path, returning every count of el_fluid_stats: tiles, cells, layer_cells
+        (fluid cells in C-PML layers summed over the three axes), skipped_stores (s22 / s33
+        stores one stress pass leaves out) and uniform_cells (fluid cells whose lambda, rho
+        and alpha come from the per-tile table)."""
+        st = FluidStats()
         flag = -1 if enable is None else (1 if enable else 0)
-        _check(lib().el_plan_fluid_path(self._h, flag, *(ctypes.byref(v) for v in out)))
-        return tuple(v.value for v in out)
+        _check(lib().el_plan_fluid_path(self._h, flag, ctypes.byref(st)))
+        return {name: int(getattr(st, name)) for name, _ in FluidStats._fields_}
 
     def timing(self, enable: bool = True):
         """Record an event pair around every time-loop kernel launch of later operations."""

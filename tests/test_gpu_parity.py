@@ -145,10 +145,16 @@ def test_negative_zero_shear_modulus():
 
 
 def _fluid_ball_scenario(seed=13, nsteps=60):
-    """192 x 40 x 40 absorbing water (mu = 0) holding a solid ball of radius 6 cells: the
-    interior tiles away from the ball take the fluid update, the others the general one."""
+    """192 x 40 x 40 absorbing fluid (mu = 0) holding a solid ball of radius 6 cells: the
+    interior tiles away from the ball take the fluid update, the others the general one.
+    The fluid is homogeneous water for x < 96 cells (uniform fluid tiles) and has random
+    lambda, rho, alpha per cell elsewhere."""
     sc = S.random_scenario((192, 40, 40), seed=seed, nsteps=nsteps, npml=4, nrec=24, fluid_fraction=1.0)
     z, y, x = np.meshgrid(np.arange(40), np.arange(40), np.arange(192), indexing="ij")
+    water = x < 96
+    sc.lam = np.where(water, np.float32(1000.0 * 1500.0 ** 2), sc.lam).astype(np.float32)
+    sc.rho = np.where(water, np.float32(1000.0), sc.rho).astype(np.float32)
+    sc.alpha = np.where(water, np.float32(1.0e5), sc.alpha).astype(np.float32)
     ball = (x - 100) ** 2 + (y - 20) ** 2 + (z - 20) ** 2 <= 36
     cp, cs, rho = 2800.0, 1500.0, 1850.0
     sc.lam = np.where(ball, rho * (cp * cp - 2 * cs * cs), sc.lam).astype(np.float32)
@@ -164,9 +170,12 @@ def test_fluid_tiles_match_general_update_and_oracle(precision, tol_same, tol_re
     Sec. 2.1): H and H^T equal the general update and the oracle."""
     sc = _fluid_ball_scenario()
     plan = el.Plan.from_scenario(sc, precision=precision)
-    tiles, cells, _, skipped = plan.fluid_counts()
-    banner(f"fluid tiles {tiles}, cells {cells} of {sc.ncells}, s22/s33 stores left out {skipped}")
+    st = plan.fluid_stats()
+    tiles, cells, skipped = st["tiles"], st["cells"], st["skipped_stores"]
+    banner(f"fluid tiles {tiles}, cells {cells} of {sc.ncells}, s22/s33 stores left out {skipped}, "
+           f"uniform-media cells {st['uniform_cells']}")
     assert tiles > 0 and 0 < cells < sc.ncells
+    assert 0 < st["uniform_cells"] < cells
     # the ball's neighbourhood leaves y and z faces next to general tiles: both bands occur
     assert 0 < skipped < 2 * cells
     p = torch.from_numpy(sc.p0)
@@ -180,9 +189,9 @@ def test_fluid_tiles_match_general_update_and_oracle(precision, tol_same, tol_re
         return tr, pa, fwd_state, adj_state
 
     tr_fast, pa_fast, fs_fast, as_fast = run()
-    assert plan.fluid_counts(False) == (0, 0, 0, 0)
+    assert set(plan.fluid_stats(False).values()) == {0}
     tr_gen, pa_gen, fs_gen, as_gen = run()
-    assert plan.fluid_counts(True) == (tiles, cells, plan.fluid_counts()[2], skipped)
+    assert plan.fluid_stats(True) == st
     banner(f"fluid vs general: traces bitwise {np.array_equal(tr_fast, tr_gen)}, "
            f"max {rel_max(tr_fast, tr_gen):.2e}; adjoint bitwise {np.array_equal(pa_fast, pa_gen)}, "
            f"max {rel_max(pa_fast, pa_gen):.2e}")

@@ -213,10 +213,13 @@ el_status el_plan_sizes(el_plan plan, int64_t *ncells, int32_t *nrec, int32_t *n
  * lambda, rho and alpha are each one value over that box (a homogeneous
  * coupling medium such as the water of Sec. 7) takes the three values from
  * a per-tile table instead of the maps, again with the same results.
+ * Inside the other tiles, every column of 1 x 1 cells by the chunk whose
+ * cells within two have mu = 0 is marked too, and its lanes run the same
+ * fluid update (storing all three normal stresses).
  */
 typedef struct el_fluid_stats {
     int64_t tiles;           /* tiles that take the fluid update                   */
-    int64_t cells;           /* their cells                                        */
+    int64_t cells;           /* cells that take it (fluid tiles and columns)       */
     int64_t layer_cells;     /* sum over the three axes of those cells in the      */
                              /* axis's C-PML layers (depth > 0): only the diagonal */
                              /* memory variable is carried there                   */
@@ -224,6 +227,7 @@ typedef struct el_fluid_stats {
                              /* stress pass leaves out                             */
     int64_t uniform_cells;   /* cells of fluid tiles with uniform lambda, rho,     */
                              /* alpha (maps not read)                              */
+    int64_t column_cells;    /* cells of fluid columns inside other tiles          */
 } el_fluid_stats;
 
 /*

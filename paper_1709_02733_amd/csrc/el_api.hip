@@ -101,6 +101,7 @@ bool layout(const el_grid &g, int nrec, Layout *L) {
         L->tile_order = take((size_t)8 * t.per * sizeof(int));
         L->tile_flags = take(2 * (size_t)t.ntiles);
         L->tile_media = take((size_t)4 * t.ntiles * es);
+        L->tile_lanes = take((size_t)kTileY * t.ntiles * 8);
     }
     L->partial = take(7 * kDotBlocks * 8);
     L->total = off;
@@ -120,6 +121,7 @@ Tiles make_tiles(int nx, int ny, int nz) {
     t.nzc = (nz + t.zc - 1) / t.zc;
     t.ntiles = t.ntx * t.nty * t.nzc;
     t.order = nullptr;
+    t.lanes = nullptr;
     t.per = 0;
     std::vector<int> cnt(8, 0);
     for (int q = 0; q < t.ntiles; ++q) ++cnt[tile_xcd(t, q)];
@@ -154,15 +156,17 @@ int tile_edges(const Tiles &t, const unsigned char *fast, int q) {
     return edges;
 }
 
-std::vector<int> tile_order(const Tiles &t, const unsigned char *fast, const unsigned char *uni) {
+std::vector<int> tile_order(const Tiles &t, const unsigned char *fast, const unsigned char *uni,
+                            const unsigned char *cols) {
     std::vector<int> order((size_t)8 * t.per, -1);
     std::vector<int> fill(8, 0);
     // tiles of an XCD in z-major order: a region's tiles are consecutive
     for (int q = 0; q < t.ntiles; ++q) {
         const int x = tile_xcd(t, q);
         const bool f = fast && fast[q];
-        order[(size_t)fill[x]++ * 8 + x] =
-            q | (f ? kFastTile | tile_edges(t, fast, q) | (uni && uni[q] ? kUniformTile : 0) : 0);
+        const int flags = f ? kFastTile | tile_edges(t, fast, q) | (uni && uni[q] ? kUniformTile : 0)
+                            : (fast && cols && cols[q] ? kColumnTile : 0);
+        order[(size_t)fill[x]++ * 8 + x] = q | flags;
     }
     return order;
 }
@@ -403,7 +407,7 @@ el_status upload_receivers(el_plan_ *p, const double *rec, hipStream_t s) {
 // tiles when the fluid update is enabled and without them otherwise.
 el_status upload_order(el_plan p, hipStream_t s) {
     const unsigned char *fast = p->fluid_path ? p->fast.data() : nullptr;
-    const std::vector<int> order = tile_order(p->tiles, fast, p->uni.data());
+    const std::vector<int> order = tile_order(p->tiles, fast, p->uni.data(), p->cols.data());
     int *dst = reinterpret_cast<int *>(p->ws + p->L.tile_order);
     HIP_TRY(hipMemcpyAsync(dst, order.data(), order.size() * sizeof(int), hipMemcpyHostToDevice, s), "tile order");
     std::vector<unsigned char> fl(p->rec_tile.size(), 0);
@@ -554,11 +558,17 @@ el_status el_plan_create(el_plan *out, const el_grid *grid, const float *lam, co
         // fluid tiles (el_kernels.hip, k_classify), then the order table
         unsigned char *flags = reinterpret_cast<unsigned char *>(p->ws + L.tile_flags);
         unsigned char *uflags = flags + p->tiles.ntiles;
+        unsigned long long *lanes = reinterpret_cast<unsigned long long *>(p->ws + L.tile_lanes);
+        p->tiles.lanes = lanes;
         e = grid->precision == EL_F64
-                ? launch_classify(p->dd, p->tiles, flags, uflags, const_cast<double *>(p->dd.med), s)
-                : launch_classify(p->df, p->tiles, flags, uflags, const_cast<float *>(p->df.med), s);
+                ? launch_classify(p->dd, p->tiles, flags, uflags, const_cast<double *>(p->dd.med), lanes, s)
+                : launch_classify(p->df, p->tiles, flags, uflags, const_cast<float *>(p->df.med), lanes, s);
         p->fast.assign(p->tiles.ntiles, 0);
         p->uni.assign(p->tiles.ntiles, 0);
+        p->cols.assign(p->tiles.ntiles, 0);
+        std::vector<unsigned long long> hl((size_t)kTileY * p->tiles.ntiles, 0);
+        if (e == hipSuccess && p->tiles.ntiles > 0)
+            e = hipMemcpyAsync(hl.data(), lanes, hl.size() * 8, hipMemcpyDeviceToHost, s);
         if (e == hipSuccess && p->tiles.ntiles > 0)
             e = hipMemcpyAsync(p->fast.data(), flags, p->fast.size(), hipMemcpyDeviceToHost, s);
         if (e == hipSuccess && p->tiles.ntiles > 0)
@@ -576,7 +586,24 @@ el_status el_plan_create(el_plan *out, const el_grid *grid, const float *lam, co
             return lo + hi;
         };
         for (int q = 0; q < t.ntiles; ++q) {
-            if (!p->fast[q]) continue;
+            if (!p->fast[q]) {
+                // fluid columns of a general tile: all their cells take the fluid update
+                const int bx = q % t.ntx, r = q / t.ntx, by = r % t.nty, bz = r / t.nty;
+                const int z0 = bz * t.zc, dep = std::min(t.zc, n[2] - z0);
+                for (int row = 0; row < kTileY; ++row) {
+                    const unsigned long long m = hl[(size_t)kTileY * q + row];
+                    if (!m) continue;
+                    p->cols[q] = 1;
+                    for (int b = 0; b < 64; ++b) {
+                        if (!((m >> b) & 1ull)) continue;
+                        const int i = bx * kTileX + b, j = by * kTileY + row;
+                        p->column_cells += dep;
+                        p->fast_layer_cells += (long long)in_layers(i, i + 1, n[0]) * dep +
+                                               (long long)in_layers(j, j + 1, n[1]) * dep + in_layers(z0, z0 + dep, n[2]);
+                    }
+                }
+                continue;
+            }
             const int bx = q % t.ntx, r = q / t.ntx, by = r % t.nty, bz = r / t.nty;
             const int c0[3] = {bx * kTileX, by * kTileY, bz * t.zc};
             const int w[3] = {std::min(kTileX, n[0] - c0[0]), std::min(kTileY, n[1] - c0[1]), std::min(t.zc, n[2] - c0[2])};
@@ -733,7 +760,8 @@ el_status el_plan_fluid_path(el_plan p, int32_t enable, el_fluid_stats *stats) {
         *stats = el_fluid_stats{};
         if (p->fluid_path) {
             stats->tiles = p->fast_tiles;
-            stats->cells = p->fast_cells;
+            stats->cells = p->fast_cells + p->column_cells;
+            stats->column_cells = p->column_cells;
             stats->layer_cells = p->fast_layer_cells;
             stats->skipped_stores = p->fast_skipped;
             stats->uniform_cells = p->uniform_cells;

@@ -115,6 +115,7 @@ struct Tiles {
     int ntiles;              // ntx * nty * nzc
     int per;                 // tiles per XCD: the grid has 8 * per blocks
     const int *order;        // device: tile of each block (-1 for a padding block)
+    const unsigned long long *lanes;   // device: per tile and row, its fluid columns (k_classify)
 };
 Tiles make_tiles(int nx, int ny, int nz);
 // XCD (0..7) that processes tile q; blocks run on XCD blockIdx % 8.
@@ -129,11 +130,15 @@ int tile_xcd(const Tiles &t, int q);
 // along such y faces and s33 only on two-plane bands along such z faces.
 // kUniformTile marks a fluid tile whose lambda, rho and alpha are constant over the cells
 // its loops read (k_classify): they come from a per-tile table instead of the maps.
+// kColumnTile marks a tile that is not fluid but has fluid columns (Tiles::lanes): the
+// lanes of those columns run the fluid update.
 constexpr int kFastTile = 1 << 30;
 constexpr int kUniformTile = 1 << 29;
+constexpr int kColumnTile = 1 << 28;
 constexpr int kEdgeShift = 24;
 constexpr int kTileMask = (1 << kEdgeShift) - 1;
-std::vector<int> tile_order(const Tiles &t, const unsigned char *fast, const unsigned char *uni);
+std::vector<int> tile_order(const Tiles &t, const unsigned char *fast, const unsigned char *uni,
+                            const unsigned char *cols);
 // Bits kEdgeShift.. of tile q's entry (0 unless q is a fluid tile).
 int tile_edges(const Tiles &t, const unsigned char *fast, int q);
 
@@ -164,6 +169,7 @@ struct Layout {
     size_t tile_order;       // tile of each stencil block
     size_t tile_flags;       // per tile: 1 if the fluid update applies; then per tile: 1 if uniform
     size_t tile_media;       // per tile: lambda, rho, alpha, 0 (elements of the plan's precision)
+    size_t tile_lanes;       // per tile and row: 64-bit mask of fluid columns
     size_t partial;          // reduction partials
     size_t total;
 };
@@ -179,7 +185,8 @@ hipError_t launch_media_stats(const float *lam, const float *mu, const float *rh
                               long long n, double dt, double *stats, double *partial, hipStream_t s);
 template <typename T> hipError_t launch_zero_state(const Dev<T> &d, hipStream_t s);
 template <typename T> hipError_t launch_classify(const Dev<T> &d, const Tiles &tl, unsigned char *fast,
-                                                 unsigned char *uni, T *med, hipStream_t s);
+                                                 unsigned char *uni, T *med, unsigned long long *lanes,
+                                                 hipStream_t s);
 template <typename T> hipError_t launch_inject(const Dev<T> &d, const T *p0, hipStream_t s);
 template <typename T> hipError_t launch_velocity(const Dev<T> &d, const Tiles &tl, hipStream_t s);
 template <typename T> hipError_t launch_stress(const Dev<T> &d, const Tiles &tl, hipStream_t s);
@@ -215,6 +222,8 @@ struct el_plan_ {
     el::Tiles tiles;
     std::vector<unsigned char> fast;   // per tile: the fluid update applies (host copy)
     std::vector<unsigned char> uni;    // per tile: fluid with uniform lambda, rho, alpha (host copy)
+    std::vector<unsigned char> cols;   // per tile: not fluid, with fluid columns (host)
+    long long column_cells = 0;        // cells of fluid columns in such tiles
     long long uniform_cells = 0;       // cells of uniform fluid tiles
     long long fast_tiles = 0, fast_cells = 0;
     long long fast_layer_cells = 0;    // sum over axes of fluid-tile cells in that axis's C-PML layers

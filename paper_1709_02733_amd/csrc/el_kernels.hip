@@ -141,6 +141,11 @@ hipError_t launch_zero_state(const Dev<T> &d, hipStream_t s) {
 // cells from the tile, out of reach of its taps).  One block per tile checks mu over that
 // box; cells outside the grid count as fluid (zero extension).
 //
+// Inside a tile that is not fluid, column (i, j) of its chunk is fluid when mu = 0 on the
+// cells within two of it (x, y in [i-2, i+2] x [j-2, j+2], z from z0-2 to z1+1, clipped to
+// the grid): bit i-x0 of lanes[4 q + j-y0], set for such columns, lets the lanes of those
+// columns run the fluid update inside the general tile.
+//
 // A fluid tile whose lambda, rho and alpha are each one value (bit for bit) over the same
 // box is also marked uniform, and its three values are written to med[4 q + 0..2]: the
 // stencil passes then take them from there instead of reading the maps (the box holds every
@@ -158,7 +163,8 @@ __device__ __forceinline__ bool same_bits<double>(double a, double b) {
 }
 
 template <typename T>
-__global__ void k_classify(Dev<T> d, Tiles tl, unsigned char *fast, unsigned char *uni, T *med) {
+__global__ __launch_bounds__(kTileX * kTileY) void k_classify(Dev<T> d, Tiles tl, unsigned char *fast,
+                                                             unsigned char *uni, T *med, unsigned long long *lanes) {
     const int q = blockIdx.x;
     if (q >= tl.ntiles) return;
     const int bx = q % tl.ntx, r = q / tl.ntx, by = r % tl.nty, bz = r / tl.nty;
@@ -182,6 +188,28 @@ __global__ void k_classify(Dev<T> d, Tiles tl, unsigned char *fast, unsigned cha
     }
     solid = __syncthreads_or(solid);
     vary = __syncthreads_or(vary);
+    // columns of the tile and two around it: does mu vanish from z0-2 to z1+1?
+    constexpr int HX = kTileX + 4, HY = kTileY + 4;
+    __shared__ unsigned char col_solid[HX * HY];
+    for (int e = threadIdx.x; e < HX * HY; e += blockDim.x) {
+        const int xx = x0 - 2 + e % HX, yy = y0 - 2 + e / HX;
+        int sol = 0;
+        if (xx >= 0 && xx < d.nx && yy >= 0 && yy < d.ny)
+            for (int zz = az; zz < min(z1 + 2, d.nz); ++zz)
+                if (d.mu[(long long)(zz + 2) * d.plane + (long long)yy * d.px + xx] != T(0)) sol = 1;
+        col_solid[e] = (unsigned char)sol;
+    }
+    __syncthreads();
+    const int lx = (int)threadIdx.x % kTileX, ly = (int)threadIdx.x / kTileX;
+    int colfluid = 0;
+    if (x0 + lx < d.nx && y0 + ly < d.ny) {
+        colfluid = 1;
+        for (int dy = 0; dy < 5; ++dy)
+            for (int dx = 0; dx < 5; ++dx)
+                if (col_solid[(ly + dy) * HX + lx + dx]) colfluid = 0;
+    }
+    const unsigned long long m = __ballot(colfluid);
+    if ((threadIdx.x & 63) == 0) lanes[4 * (size_t)q + threadIdx.x / 64] = m;
     if (threadIdx.x == 0) {
         fast[q] = solid ? 0 : 1;
         uni[q] = solid || vary ? 0 : 1;
@@ -194,9 +222,10 @@ __global__ void k_classify(Dev<T> d, Tiles tl, unsigned char *fast, unsigned cha
 
 template <typename T>
 hipError_t launch_classify(const Dev<T> &d, const Tiles &tl, unsigned char *fast, unsigned char *uni, T *med,
-                           hipStream_t s) {
+                           unsigned long long *lanes, hipStream_t s) {
+    static_assert(kTileX == 64 && kTileY == 4, "one wavefront per tile row");
     if (tl.ntiles == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_classify<T>, dim3(tl.ntiles), dim3(256), 0, s, d, tl, fast, uni, med);
+    hipLaunchKernelGGL(k_classify<T>, dim3(tl.ntiles), dim3(kTileX * kTileY), 0, s, d, tl, fast, uni, med, lanes);
     return hipGetLastError();
 }
 
@@ -454,7 +483,7 @@ hipError_t launch_dot(const T *a, const T *b, long long n, double *partial, doub
                                                const float *, hipStream_t);                                          \
     template hipError_t launch_zero_state<T>(const Dev<T> &, hipStream_t);                                           \
     template hipError_t launch_classify<T>(const Dev<T> &, const Tiles &, unsigned char *, unsigned char *, T *,     \
-                                           hipStream_t);                                                             \
+                                           unsigned long long *, hipStream_t);                                       \
     template hipError_t launch_inject<T>(const Dev<T> &, const T *, hipStream_t);                                    \
     template hipError_t launch_gather<T>(const Dev<T> &, const Rec &, double *, hipStream_t);                        \
     template hipError_t launch_scatter<T>(const Dev<T> &, const Rec &, const double *, hipStream_t);                 \

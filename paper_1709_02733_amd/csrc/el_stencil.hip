@@ -120,15 +120,16 @@ __device__ __forceinline__ T harmonic4r(T r0, T r1, T r2, T r3) {
 }
 
 // Tile t of this block from the XCD-balanced order table; false for padding blocks.  fast is
-// set for a fluid tile (see k_classify), uni for a fluid tile of uniform media, edges to its
-// face neighbours that take the general update (bits 0, 1: lower and upper side along y;
-// bits 2, 3: along z).
+// set for a fluid tile (see k_classify), uni for a fluid tile of uniform media, cols for a
+// general tile with fluid columns, edges to the face neighbours of a fluid tile that take
+// the general update (bits 0, 1: lower and upper side along y; bits 2, 3: along z).
 __device__ __forceinline__ bool tile_of(const Tiles &tl, int nz, int &x0, int &y0, int &z0, int &z1, int &t,
-                                        bool &fast, bool &uni, int &edges) {
+                                        bool &fast, bool &uni, bool &cols, int &edges) {
     const int ent = tl.order[blockIdx.x];
     if (ent < 0) return false;
     fast = (ent & kFastTile) != 0;
     uni = (ent & kUniformTile) != 0;
+    cols = (ent & kColumnTile) != 0;
     edges = (ent >> kEdgeShift) & 15;
     t = ent & kTileMask;
     const int bx = t % tl.ntx;
@@ -173,26 +174,36 @@ __device__ __forceinline__ void fluid_vel(const Dev<T> &d, int i, int j, int z0,
     qs[3] = ldb(s11, o + sz);
     const T rho_t = UNI ? d.med[4 * t + 1] : T(0), alp_t = UNI ? d.med[4 * t + 2] : T(0);
     T rho_k = UNI ? rho_t : ldb(d.rho, o), alp_k = UNI ? alp_t : ldb(d.alpha, o);
-    for (int k = z0; k < z1; ++k, o += sz) {
-#pragma unroll
-        for (int n = 0; n < 3; ++n) qs[n] = qs[n + 1];
-        qs[3] = ldb(s11, o + 2 * sz);
-        T a11[4], b11[4];
+    // The main inputs of plane k + 1 are loaded before plane k is computed (two planes of
+    // loads in flight per wavefront); none of them is written by this pass.
+    struct Plane {
+        T qn, a11[4], b11[4], uold[3], rho_n[3], alp_n[3];
+    };
+    auto load = [&](Plane &p, unsigned oo) {
+        p.qn = ldb(s11, oo + 2 * sz);
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            a11[q] = ldb(s11, o + (unsigned)(q - 1) * sx);
-            b11[q] = ldb(s11, o + (unsigned)(q - 1) * sy);
+            p.a11[q] = ldb(s11, oo + (unsigned)(q - 1) * sx);
+            p.b11[q] = ldb(s11, oo + (unsigned)(q - 1) * sy);
         }
-        T uold[3], rho_n[3], alp_n[3];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) uold[c] = ldb(d.f[U1 + c], o);
-        rho_n[0] = UNI ? rho_t : ldb(d.rho, o + sx);
-        rho_n[1] = UNI ? rho_t : ldb(d.rho, o + sy);
-        rho_n[2] = UNI ? rho_t : ldb(d.rho, o + sz);
-        alp_n[0] = UNI ? alp_t : ldb(d.alpha, o + sx);
-        alp_n[1] = UNI ? alp_t : ldb(d.alpha, o + sy);
-        alp_n[2] = UNI ? alp_t : ldb(d.alpha, o + sz);
+        for (int c = 0; c < 3; ++c) p.uold[c] = ldb(d.f[U1 + c], oo);
+        p.rho_n[0] = UNI ? rho_t : ldb(d.rho, oo + sx);
+        p.rho_n[1] = UNI ? rho_t : ldb(d.rho, oo + sy);
+        p.rho_n[2] = UNI ? rho_t : ldb(d.rho, oo + sz);
+        p.alp_n[0] = UNI ? alp_t : ldb(d.alpha, oo + sx);
+        p.alp_n[1] = UNI ? alp_t : ldb(d.alpha, oo + sy);
+        p.alp_n[2] = UNI ? alp_t : ldb(d.alpha, oo + sz);
+    };
+    Plane cur{}, nxt{};
+    load(cur, o);
+    for (int k = z0; k < z1; ++k, o += sz) {
+        if (k + 1 < z1) load(nxt, o + sz);
         __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int n = 0; n < 3; ++n) qs[n] = qs[n + 1];
+        qs[3] = cur.qn;
+        const T *a11 = cur.a11, *b11 = cur.b11, *uold = cur.uold, *rho_n = cur.rho_n, *alp_n = cur.alp_n;
         T acc[3];
         acc[0] = dplus(a11[0], a11[1], a11[2], a11[3], h);
         acc[1] = dplus(b11[0], b11[1], b11[2], b11[3], h);
@@ -241,14 +252,15 @@ __device__ __forceinline__ void fluid_vel(const Dev<T> &d, int i, int j, int z0,
                 if (tw >= 0) stb(d.mem[a][a], slab_byte(d, a, tw, i, j, k), g);
             }
         }
+        cur = nxt;
     }
 }
 
 template <typename T, bool ADJ>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 5 : 1))) void k_vel(Dev<T> d, Tiles tl) {
     int x0, y0, z0, z1, t = 0, edges = 0;
-    bool fast = false, uni = false;
-    if (!tile_of(tl, d.nz, x0, y0, z0, z1, t, fast, uni, edges)) return;
+    bool fast = false, uni = false, cols = false;
+    if (!tile_of(tl, d.nz, x0, y0, z0, z1, t, fast, uni, cols, edges)) return;
     const int i = x0 + (int)threadIdx.x % TX, j = y0 + (int)threadIdx.x / TX;
     if (i >= d.nx || j >= d.ny) return;
     const T h = d.inv_dx, dt = d.dt;
@@ -261,6 +273,10 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
     if (fast) {
         if (uni) fluid_vel<T, ADJ, true>(d, i, j, z0, z1, o, t, snx, sny, sox, soy);
         else fluid_vel<T, ADJ, false>(d, i, j, z0, z1, o, t, snx, sny, sox, soy);
+        return;
+    }
+    if (cols && ((tl.lanes[kTileY * t + (int)threadIdx.x / TX] >> ((int)threadIdx.x % TX)) & 1ull)) {
+        fluid_vel<T, ADJ, false>(d, i, j, z0, z1, o, t, snx, sny, sox, soy);   // fluid column
         return;
     }
     T qa[4], qb[4], qc[4];   // s13, s23 at planes k-2..k+1; s33 at planes k-1..k+2
@@ -391,10 +407,11 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
 //   axis x: c=0 Dm, c=1 Dp, c=2 Dp;  axis y: c=0 Dp, c=1 Dm, c=2 Dp;  axis z: c=0 Dp, c=1 Dp, c=2 Dm
 // ------------------------------------------------------------------------
 // Fluid-tile loop of the stress-shaped pass.  UNI: a uniform tile, whose lambda comes from
-// the per-tile table instead of the map (the same value, so the same results).
+// the per-tile table instead of the map (the same value, so the same results).  keep: store
+// s22 and s33 on every cell (a fluid column of a general tile), else only on the bands.
 template <typename T, bool ADJ, bool UNI>
 __device__ __forceinline__ void fluid_str(const Dev<T> &d, int i, int j, int y0, int z0, int z1, unsigned o,
-                                          int t, int edges, int snx, int sny, int sox, int soy) {
+                                          int t, int edges, bool keep, int snx, int sny, int sox, int soy) {
     const T h = d.inv_dx, dt = d.dt;
     const unsigned sx = sizeof(T), sy = d.sy, sz = d.sz;
     const T *u1 = d.f[U1], *u2 = d.f[U2], *u3 = d.f[U3];
@@ -404,26 +421,38 @@ __device__ __forceinline__ void fluid_str(const Dev<T> &d, int i, int j, int y0,
     // and the shear stresses stay zero (not written).  Only the diagonal C-PML memory
     // variables (psi^{cc}; in the adjoint a phi~^{cc} and a psi~^{cc}) act on the trace.
     // s22 is stored on the rows, s33 on the planes, that general tiles read across a face
-    const bool put22 = ((edges & 1) && j < y0 + 2) || ((edges & 2) && j >= y0 + TY - 2);
-    const int zlo = (edges & 4) ? z0 + 2 : z0, zhi = (edges & 8) ? z1 - 2 : z1;
+    const bool put22 = keep || ((edges & 1) && j < y0 + 2) || ((edges & 2) && j >= y0 + TY - 2);
+    const int zlo = keep ? z1 : ((edges & 4) ? z0 + 2 : z0), zhi = keep ? z0 : ((edges & 8) ? z1 - 2 : z1);
     T qc[4];   // u3 at planes k-2..k+1
     qc[0] = T(0);
     qc[1] = ldb(u3, o - 2 * sz);
     qc[2] = ldb(u3, o - sz);
     qc[3] = ldb(u3, o);
-    for (int k = z0; k < z1; ++k, o += sz) {
-#pragma unroll
-        for (int n = 0; n < 3; ++n) qc[n] = qc[n + 1];
-        qc[3] = ldb(u3, o + sz);
-        T a1[4], b2[4];
+    // The main inputs of plane k + 1 are loaded before plane k is computed; s11 of a plane
+    // is read and written by its own lane only.
+    struct Plane {
+        T qn, a1[4], b2[4], sold, lam;
+    };
+    auto load = [&](Plane &p, unsigned oo) {
+        p.qn = ldb(u3, oo + sz);
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            a1[q] = ldb(u1, o + (unsigned)(q - 2) * sx);
-            b2[q] = ldb(u2, o + (unsigned)(q - 2) * sy);
+            p.a1[q] = ldb(u1, oo + (unsigned)(q - 2) * sx);
+            p.b2[q] = ldb(u2, oo + (unsigned)(q - 2) * sy);
         }
-        const T sold = ldb(d.f[S11], o);
-        const T lam = UNI ? lam_t : ldb(d.lam, o);
+        p.sold = ldb(d.f[S11], oo);
+        p.lam = UNI ? lam_t : ldb(d.lam, oo);
+    };
+    Plane cur{}, nxt{};
+    load(cur, o);
+    for (int k = z0; k < z1; ++k, o += sz) {
+        if (k + 1 < z1) load(nxt, o + sz);
         __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int n = 0; n < 3; ++n) qc[n] = qc[n + 1];
+        qc[3] = cur.qn;
+        const T *a1 = cur.a1, *b2 = cur.b2;
+        const T sold = cur.sold, lam = cur.lam;
         T e[3];
         e[0] = dminus(a1[0], a1[1], a1[2], a1[3], h);
         e[1] = dminus(b2[0], b2[1], b2[2], b2[3], h);
@@ -465,14 +494,15 @@ __device__ __forceinline__ void fluid_str(const Dev<T> &d, int i, int j, int y0,
                 if (tw >= 0) stb(d.mem[a][3 + a], slab_byte(d, a, tw, i, j, k), g);
             }
         }
+        cur = nxt;
     }
 }
 
 template <typename T, bool ADJ>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 5 : 1))) void k_str(Dev<T> d, Tiles tl) {
     int x0, y0, z0, z1, t = 0, edges = 0;
-    bool fast = false, uni = false;
-    if (!tile_of(tl, d.nz, x0, y0, z0, z1, t, fast, uni, edges)) return;
+    bool fast = false, uni = false, cols = false;
+    if (!tile_of(tl, d.nz, x0, y0, z0, z1, t, fast, uni, cols, edges)) return;
     const int i = x0 + (int)threadIdx.x % TX, j = y0 + (int)threadIdx.x / TX;
     if (i >= d.nx || j >= d.ny) return;
     const T h = d.inv_dx, dt = d.dt;
@@ -483,8 +513,13 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
     const int snx = pml ? slab_near(i, d.P, d.hi[0]) : -1, sny = pml ? slab_near(j, d.P, d.hi[1]) : -1;
     const int sox = pml ? slab_own(i, d.P, d.hi[0]) : -1, soy = pml ? slab_own(j, d.P, d.hi[1]) : -1;
     if (fast) {
-        if (uni) fluid_str<T, ADJ, true>(d, i, j, y0, z0, z1, o, t, edges, snx, sny, sox, soy);
-        else fluid_str<T, ADJ, false>(d, i, j, y0, z0, z1, o, t, edges, snx, sny, sox, soy);
+        if (uni) fluid_str<T, ADJ, true>(d, i, j, y0, z0, z1, o, t, edges, false, snx, sny, sox, soy);
+        else fluid_str<T, ADJ, false>(d, i, j, y0, z0, z1, o, t, edges, false, snx, sny, sox, soy);
+        return;
+    }
+    if (cols && ((tl.lanes[kTileY * t + (int)threadIdx.x / TX] >> ((int)threadIdx.x % TX)) & 1ull)) {
+        // fluid column of a general tile: its neighbours read s22 and s33, so all are stored
+        fluid_str<T, ADJ, false>(d, i, j, y0, z0, z1, o, t, 0, true, snx, sny, sox, soy);
         return;
     }
     T qa[4], qb[4], qc[4];   // u1, u2 at planes k-1..k+2; u3 at planes k-2..k+1
@@ -640,8 +675,8 @@ hipError_t launch_adj_stress(const Dev<T> &d, const Tiles &tl, hipStream_t s) {
 template <typename T>
 __global__ __launch_bounds__(NT) void k_fluid_fill(Dev<T> d, Tiles tl) {
     int x0, y0, z0, z1, t = 0, edges = 0;
-    bool fast = false, uni = false;
-    if (!tile_of(tl, d.nz, x0, y0, z0, z1, t, fast, uni, edges) || !fast) return;
+    bool fast = false, uni = false, cols = false;
+    if (!tile_of(tl, d.nz, x0, y0, z0, z1, t, fast, uni, cols, edges) || !fast) return;
     const int i = x0 + (int)threadIdx.x % TX, j = y0 + (int)threadIdx.x / TX;
     if (i >= d.nx || j >= d.ny) return;
     unsigned o = d.origin + (unsigned)z0 * d.sz + (unsigned)j * d.sy + (unsigned)i * (unsigned)sizeof(T);

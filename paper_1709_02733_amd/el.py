@@ -39,7 +39,8 @@ class Grid(ctypes.Structure):
 class FluidStats(ctypes.Structure):
     """el_fluid_stats (include/el.h)."""
     _fields_ = [("tiles", ctypes.c_int64), ("cells", ctypes.c_int64), ("layer_cells", ctypes.c_int64),
-                ("skipped_stores", ctypes.c_int64), ("uniform_cells", ctypes.c_int64)]
+                ("skipped_stores", ctypes.c_int64), ("uniform_cells", ctypes.c_int64),
+                ("column_cells", ctypes.c_int64)]
 
 
 _lib = None
@@ -248,8 +249,9 @@ class Plan:
     def fluid_stats(self, enable: bool | None = None) -> dict:
         """As fluid_path, returning every count of el_fluid_stats: tiles, cells, layer_cells
         (fluid cells in C-PML layers summed over the three axes), skipped_stores (s22 / s33
-        stores one stress pass leaves out) and uniform_cells (fluid cells whose lambda, rho
-        and alpha come from the per-tile table)."""
+        stores one stress pass leaves out), uniform_cells (fluid cells whose lambda, rho
+        and alpha come from the per-tile table) and column_cells (cells of fluid columns
+        inside tiles that are not fluid; counted in cells too)."""
         st = FluidStats()
         flag = -1 if enable is None else (1 if enable else 0)
         _check(lib().el_plan_fluid_path(self._h, flag, ctypes.byref(st)))

@@ -173,9 +173,11 @@ def test_fluid_tiles_match_general_update_and_oracle(precision, tol_same, tol_re
     st = plan.fluid_stats()
     tiles, cells, skipped = st["tiles"], st["cells"], st["skipped_stores"]
     banner(f"fluid tiles {tiles}, cells {cells} of {sc.ncells}, s22/s33 stores left out {skipped}, "
-           f"uniform-media cells {st['uniform_cells']}")
+           f"uniform-media cells {st['uniform_cells']}, fluid-column cells {st['column_cells']}")
     assert tiles > 0 and 0 < cells < sc.ncells
     assert 0 < st["uniform_cells"] < cells
+    # the tiles around the ball hold fluid columns: those lanes take the fluid update too
+    assert 0 < st["column_cells"] < cells
     # the ball's neighbourhood leaves y and z faces next to general tiles: both bands occur
     assert 0 < skipped < 2 * cells
     p = torch.from_numpy(sc.p0)

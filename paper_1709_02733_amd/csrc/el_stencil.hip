@@ -156,6 +156,17 @@ __device__ __forceinline__ bool tile_of(const Tiles &tl, int nz, int &x0, int &y
 // ------------------------------------------------------------------------
 // Fluid-tile loop of the velocity-shaped pass.  UNI: a uniform tile, whose rho and alpha
 // come from the per-tile table instead of the maps (the same values, so the same results).
+//
+// fluid tile: s22 = s33 = s11 and the shear stresses are zero on every tap, so the three
+// nonzero differences are those of s11 along x, y and z.  Of the C-PML memory variables
+// only the diagonal ones (phi^{cc}; in the adjoint a psi~^{cc} and a phi~^{cc}) act on
+// fluid cells: the others stay zero or meet only zero moduli.
+//
+// Every input of plane k + 1, the own-point memory variable included, is loaded before
+// plane k is computed (two planes of loads in flight per wavefront).  None of them is
+// written by this pass except that memory variable, which only this lane reads and writes.
+// The adjoint's taps of a psi~ are loaded with the plane's arithmetic, in one batch ahead
+// of its first store (prefetching them too costs more registers than it saves).
 template <typename T, bool ADJ, bool UNI>
 __device__ __forceinline__ void fluid_vel(const Dev<T> &d, int i, int j, int z0, int z1, unsigned o, int t,
                                           int snx, int sny, int sox, int soy) {
@@ -163,10 +174,6 @@ __device__ __forceinline__ void fluid_vel(const Dev<T> &d, int i, int j, int z0,
     const unsigned sx = sizeof(T), sy = d.sy, sz = d.sz;
     const T *s11 = d.f[S11];
     const bool pml = d.P > 0;
-    // fluid tile: s22 = s33 = s11 and the shear stresses are zero on every tap, so the
-    // three nonzero differences are those of s11 along x, y and z.  Of the C-PML memory
-    // variables only the diagonal ones (phi^{cc}; in the adjoint a psi~^{cc} and
-    // a phi~^{cc}) act on fluid cells: the others stay zero or meet only zero moduli.
     T qs[4];   // s11 at planes k-1..k+2
     qs[0] = T(0);
     qs[1] = ldb(s11, o - sz);
@@ -174,12 +181,16 @@ __device__ __forceinline__ void fluid_vel(const Dev<T> &d, int i, int j, int z0,
     qs[3] = ldb(s11, o + sz);
     const T rho_t = UNI ? d.med[4 * t + 1] : T(0), alp_t = UNI ? d.med[4 * t + 2] : T(0);
     T rho_k = UNI ? rho_t : ldb(d.rho, o), alp_k = UNI ? alp_t : ldb(d.alpha, o);
-    // The main inputs of plane k + 1 are loaded before plane k is computed (two planes of
-    // loads in flight per wavefront); none of them is written by this pass.
+    // layer coefficients of the column's x and y positions (half points)
+    const T pa_x = sox >= 0 ? d.pa[0][1][i] : T(0), pb_x = sox >= 0 ? d.pb[0][1][i] : T(0);
+    const T pa_y = soy >= 0 ? d.pa[1][1][j] : T(0), pb_y = soy >= 0 ? d.pb[1][1][j] : T(0);
     struct Plane {
         T qn, a11[4], b11[4], uold[3], rho_n[3], alp_n[3];
+        T own[3];       // forward phi^{aa}, adjoint a phi~^{aa}, at the own slab point
+        T pa_z, pb_z;
+        int so_z;
     };
-    auto load = [&](Plane &p, unsigned oo) {
+    auto load = [&](Plane &p, unsigned oo, int kk) {
         p.qn = ldb(s11, oo + 2 * sz);
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
@@ -194,11 +205,18 @@ __device__ __forceinline__ void fluid_vel(const Dev<T> &d, int i, int j, int z0,
         p.alp_n[0] = UNI ? alp_t : ldb(d.alpha, oo + sx);
         p.alp_n[1] = UNI ? alp_t : ldb(d.alpha, oo + sy);
         p.alp_n[2] = UNI ? alp_t : ldb(d.alpha, oo + sz);
+        p.so_z = pml ? slab_own(kk, d.P, d.hi[2]) : -1;
+        p.pa_z = p.so_z >= 0 ? d.pa[2][1][kk] : T(0);
+        p.pb_z = p.so_z >= 0 ? d.pb[2][1][kk] : T(0);
+        const int so[3] = {sox, soy, p.so_z};
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+            p.own[a] = so[a] >= 0 ? ldb(d.mem[a][a], slab_byte(d, a, so[a], i, j, kk)) : T(0);
     };
     Plane cur{}, nxt{};
-    load(cur, o);
+    load(cur, o, z0);
     for (int k = z0; k < z1; ++k, o += sz) {
-        if (k + 1 < z1) load(nxt, o + sz);
+        if (k + 1 < z1) load(nxt, o + sz, k + 1);
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int n = 0; n < 3; ++n) qs[n] = qs[n + 1];
@@ -209,7 +227,8 @@ __device__ __forceinline__ void fluid_vel(const Dev<T> &d, int i, int j, int z0,
         acc[1] = dplus(b11[0], b11[1], b11[2], b11[3], h);
         acc[2] = dplus(qs[0], qs[1], qs[2], qs[3], h);
         const int crd[3] = {i, j, k};
-        const int slab[3] = {sox, soy, pml ? slab_own(k, d.P, d.hi[2]) : -1};
+        const int slab[3] = {sox, soy, cur.so_z};
+        const T pa[3] = {pa_x, pa_y, cur.pa_z}, pb[3] = {pb_x, pb_y, cur.pb_z};
         if (ADJ) {
 #pragma unroll
             for (int c = 0; c < 3; ++c) acc[c] *= dt;
@@ -222,9 +241,8 @@ __device__ __forceinline__ void fluid_vel(const Dev<T> &d, int i, int j, int z0,
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
                 if (slab[a] < 0) continue;
-                const unsigned q = slab_byte(d, a, slab[a], i, j, k);
-                const T phi = d.pb[a][1][crd[a]] * ldb(d.mem[a][a], q) + d.pa[a][1][crd[a]] * acc[a];
-                stb(d.mem[a][a], q, phi);
+                const T phi = pb[a] * cur.own[a] + pa[a] * acc[a];
+                stb(d.mem[a][a], slab_byte(d, a, slab[a], i, j, k), phi);
                 acc[a] += phi;
             }
         }
@@ -245,10 +263,9 @@ __device__ __forceinline__ void fluid_vel(const Dev<T> &d, int i, int j, int z0,
             for (int a = 0; a < 3; ++a) {
                 if (slab[a] < 0) continue;
                 // g' = a phi~^{aa} <- b g' + a dt r^a
-                const unsigned q = slab_byte(d, a, slab[a], i, j, k);
                 const int tw = slab_twin(crd[a], d.P, d.hi[a]);
-                const T g = d.pb[a][1][crd[a]] * ldb(d.mem[a][a], q) + d.pa[a][1][crd[a]] * dt * out[a];
-                stb(d.mem[a][a], q, g);
+                const T g = pb[a] * cur.own[a] + pa[a] * dt * out[a];
+                stb(d.mem[a][a], slab_byte(d, a, slab[a], i, j, k), g);
                 if (tw >= 0) stb(d.mem[a][a], slab_byte(d, a, tw, i, j, k), g);
             }
         }
@@ -409,6 +426,12 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
 // Fluid-tile loop of the stress-shaped pass.  UNI: a uniform tile, whose lambda comes from
 // the per-tile table instead of the map (the same value, so the same results).  keep: store
 // s22 and s33 on every cell (a fluid column of a general tile), else only on the bands.
+//
+// fluid tile: mu = 0, so the three normal stresses take the same increment lambda tr and
+// the shear stresses stay zero (not written).  Only the diagonal C-PML memory variables
+// (psi^{cc}; in the adjoint a phi~^{cc} and a psi~^{cc}) act on the trace.  As in the
+// velocity loop, every input of plane k + 1 is loaded before plane k is computed; s11 and
+// the own-point memory variable of a cell are read and written by its own lane only.
 template <typename T, bool ADJ, bool UNI>
 __device__ __forceinline__ void fluid_str(const Dev<T> &d, int i, int j, int y0, int z0, int z1, unsigned o,
                                           int t, int edges, bool keep, int snx, int sny, int sox, int soy) {
@@ -417,9 +440,6 @@ __device__ __forceinline__ void fluid_str(const Dev<T> &d, int i, int j, int y0,
     const T *u1 = d.f[U1], *u2 = d.f[U2], *u3 = d.f[U3];
     const bool pml = d.P > 0;
     const T lam_t = UNI ? d.med[4 * t] : T(0);
-    // fluid tile: mu = 0, so the three normal stresses take the same increment lambda tr
-    // and the shear stresses stay zero (not written).  Only the diagonal C-PML memory
-    // variables (psi^{cc}; in the adjoint a phi~^{cc} and a psi~^{cc}) act on the trace.
     // s22 is stored on the rows, s33 on the planes, that general tiles read across a face
     const bool put22 = keep || ((edges & 1) && j < y0 + 2) || ((edges & 2) && j >= y0 + TY - 2);
     const int zlo = keep ? z1 : ((edges & 4) ? z0 + 2 : z0), zhi = keep ? z0 : ((edges & 8) ? z1 - 2 : z1);
@@ -428,12 +448,17 @@ __device__ __forceinline__ void fluid_str(const Dev<T> &d, int i, int j, int y0,
     qc[1] = ldb(u3, o - 2 * sz);
     qc[2] = ldb(u3, o - sz);
     qc[3] = ldb(u3, o);
-    // The main inputs of plane k + 1 are loaded before plane k is computed; s11 of a plane
-    // is read and written by its own lane only.
+    // layer coefficients of the column's x and y positions (integer points)
+    const T pa_x = sox >= 0 ? d.pa[0][0][i] : T(0), pb_x = sox >= 0 ? d.pb[0][0][i] : T(0);
+    const T pa_y = soy >= 0 ? d.pa[1][0][j] : T(0), pb_y = soy >= 0 ? d.pb[1][0][j] : T(0);
     struct Plane {
         T qn, a1[4], b2[4], sold, lam;
+        T own[3];       // forward psi^{aa}, adjoint a psi~^{aa}, at the own slab point
+        T near[3][4];   // adjoint: taps of a phi~^{aa} (Dm) where they reach a layer
+        T pa_z, pb_z;
+        int so_z, sn_z;
     };
-    auto load = [&](Plane &p, unsigned oo) {
+    auto load = [&](Plane &p, unsigned oo, int kk) {
         p.qn = ldb(u3, oo + sz);
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
@@ -442,11 +467,33 @@ __device__ __forceinline__ void fluid_str(const Dev<T> &d, int i, int j, int y0,
         }
         p.sold = ldb(d.f[S11], oo);
         p.lam = UNI ? lam_t : ldb(d.lam, oo);
+        p.so_z = pml ? slab_own(kk, d.P, d.hi[2]) : -1;
+        p.sn_z = ADJ && pml ? slab_near(kk, d.P, d.hi[2]) : -1;
+        p.pa_z = p.so_z >= 0 ? d.pa[2][0][kk] : T(0);
+        p.pb_z = p.so_z >= 0 ? d.pb[2][0][kk] : T(0);
+        const int so[3] = {sox, soy, p.so_z}, sn[3] = {snx, sny, p.sn_z};
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            p.own[a] = so[a] >= 0 ? ldb(d.mem[a][3 + a], slab_byte(d, a, so[a], i, j, kk)) : T(0);
+            if (ADJ) {
+                if (sn[a] >= 0) {
+                    const unsigned q = slab_byte(d, a, sn[a], i, j, kk), st = slab_stride(d, a);
+                    const T *g = d.mem[a][a];
+                    p.near[a][0] = ldb(g, q - 2 * st);
+                    p.near[a][1] = ldb(g, q - st);
+                    p.near[a][2] = ldb(g, q);
+                    p.near[a][3] = ldb(g, q + st);
+                } else {
+#pragma unroll
+                    for (int n = 0; n < 4; ++n) p.near[a][n] = T(0);
+                }
+            }
+        }
     };
     Plane cur{}, nxt{};
-    load(cur, o);
+    load(cur, o, z0);
     for (int k = z0; k < z1; ++k, o += sz) {
-        if (k + 1 < z1) load(nxt, o + sz);
+        if (k + 1 < z1) load(nxt, o + sz, k + 1);
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int n = 0; n < 3; ++n) qc[n] = qc[n + 1];
@@ -458,22 +505,21 @@ __device__ __forceinline__ void fluid_str(const Dev<T> &d, int i, int j, int y0,
         e[1] = dminus(b2[0], b2[1], b2[2], b2[3], h);
         e[2] = dminus(qc[0], qc[1], qc[2], qc[3], h);
         const int crd[3] = {i, j, k};
-        const int slab[3] = {sox, soy, pml ? slab_own(k, d.P, d.hi[2]) : -1};
+        const int slab[3] = {sox, soy, cur.so_z};
+        const T pa[3] = {pa_x, pa_y, cur.pa_z}, pb[3] = {pb_x, pb_y, cur.pb_z};
         if (ADJ) {
 #pragma unroll
             for (int a = 0; a < 3; ++a) e[a] *= dt;
-            const int near[3] = {snx, sny, pml ? slab_near(k, d.P, d.hi[2]) : -1};
+            const int near[3] = {snx, sny, cur.sn_z};
 #pragma unroll
             for (int a = 0; a < 3; ++a)
-                if (near[a] >= 0)
-                    e[a] += dm_at(d.mem[a][a], slab_byte(d, a, near[a], i, j, k), slab_stride(d, a), h);
+                if (near[a] >= 0) e[a] += dminus(cur.near[a][0], cur.near[a][1], cur.near[a][2], cur.near[a][3], h);
         } else {
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
                 if (slab[a] < 0) continue;
-                const unsigned q = slab_byte(d, a, slab[a], i, j, k);
-                const T psi = d.pb[a][0][crd[a]] * ldb(d.mem[a][3 + a], q) + d.pa[a][0][crd[a]] * e[a];
-                stb(d.mem[a][3 + a], q, psi);
+                const T psi = pb[a] * cur.own[a] + pa[a] * e[a];
+                stb(d.mem[a][3 + a], slab_byte(d, a, slab[a], i, j, k), psi);
                 e[a] += psi;
             }
         }
@@ -487,10 +533,9 @@ __device__ __forceinline__ void fluid_str(const Dev<T> &d, int i, int j, int y0,
             for (int a = 0; a < 3; ++a) {
                 if (slab[a] < 0) continue;
                 // g = a psi~^{aa} <- b g + a dt w_aa
-                const unsigned q = slab_byte(d, a, slab[a], i, j, k);
                 const int tw = slab_twin(crd[a], d.P, d.hi[a]);
-                const T g = d.pb[a][0][crd[a]] * ldb(d.mem[a][3 + a], q) + d.pa[a][0][crd[a]] * dt * w;
-                stb(d.mem[a][3 + a], q, g);
+                const T g = pb[a] * cur.own[a] + pa[a] * dt * w;
+                stb(d.mem[a][3 + a], slab_byte(d, a, slab[a], i, j, k), g);
                 if (tw >= 0) stb(d.mem[a][3 + a], slab_byte(d, a, tw, i, j, k), g);
             }
         }

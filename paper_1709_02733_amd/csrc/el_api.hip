@@ -108,11 +108,11 @@ bool layout(const el_grid &g, int nrec, Layout *L) {
     return true;
 }
 
-// Tiles of kTileX x kTileY columns by chunks of kZChunk planes (measured at 384^3 with
-// fluid tiles: chunks of 4 planes beat 8 by 1% and 16 by 5%; the many short blocks keep
-// the XCDs evenly loaded).  The grid has 8 * per blocks; tile_order() says which tile
-// each block processes.
-constexpr int kZChunk = 4;
+// Tiles of kTileX x kTileY columns by chunks of kZChunk planes (measured at 384^3 with the
+// fluid update and its pipelined loops: chunks of 6 planes beat 4 by 1.2%, 8 by 0.5% and 12
+// by 1.7%; short blocks keep the XCDs evenly loaded, long ones re-read fewer halo planes).
+// The grid has 8 * per blocks; tile_order() says which tile each block processes.
+constexpr int kZChunk = 6;
 Tiles make_tiles(int nx, int ny, int nz) {
     Tiles t;
     t.ntx = (nx + kTileX - 1) / kTileX;

@@ -65,6 +65,30 @@ __device__ __forceinline__ void stb(T *base, unsigned off, T v) {
     *reinterpret_cast<T *>(reinterpret_cast<char *>(base) + off) = v;
 }
 
+// Load unless off (then zero): the load is issued under the lane mask, so lanes that do not
+// need the value move no bytes.
+template <typename T>
+__device__ __forceinline__ T ld_if(bool on, const T *base, unsigned off) {
+    T v = T(0);
+    if (on) v = ldb(base, off);
+    return v;
+}
+
+// Fluid columns of a general tile (Tiles::lanes).  A row whose columns are all fluid runs
+// the fluid loop (returns true after doing so); in a mixed row the fluid lanes run the
+// general loop with *fl set: the loads they do not need are masked off (their shear taps
+// are zero, and s22 = s33 = s11 on their taps, so those taps are read from s11).
+__device__ __forceinline__ bool fluid_row(const Tiles &tl, int t, int x0, int nx, bool cols, bool &fl) {
+    fl = false;
+    if (!cols) return false;
+    const unsigned long long m = tl.lanes[kTileY * t + (int)threadIdx.x / TX];
+    const int nv = min(TX, nx - x0);
+    const unsigned long long valid = nv >= 64 ? ~0ull : ((1ull << nv) - 1ull);
+    if (m == valid) return true;
+    fl = ((m >> ((int)threadIdx.x % TX)) & 1ull) != 0;
+    return false;
+}
+
 // 4th-order staggered differences (Sec. 2.2, eq. derivative):
 //   Dp: value at i + 1/2 from samples i-1, i, i+1, i+2;  Dm: value at i from samples i-2 .. i+1.
 template <typename T>
@@ -292,21 +316,26 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
         else fluid_vel<T, ADJ, false>(d, i, j, z0, z1, o, t, snx, sny, sox, soy);
         return;
     }
-    if (cols && ((tl.lanes[kTileY * t + (int)threadIdx.x / TX] >> ((int)threadIdx.x % TX)) & 1ull)) {
-        fluid_vel<T, ADJ, false>(d, i, j, z0, z1, o, t, snx, sny, sox, soy);   // fluid column
+    bool fl;
+    if (fluid_row(tl, t, x0, d.nx, cols, fl) || (ADJ && fl)) {
+        // the adjoint's general loop has no registers to spare for the masked loads, so its
+        // fluid lanes of a mixed row run the fluid loop (the row executes both loops)
+        fluid_vel<T, ADJ, false>(d, i, j, z0, z1, o, t, snx, sny, sox, soy);
         return;
     }
+    const bool sh = !fl;                     // this lane reads the shear stresses
+    const T *p22 = fl ? s11 : s22, *p33 = fl ? s11 : s33;
     T qa[4], qb[4], qc[4];   // s13, s23 at planes k-2..k+1; s33 at planes k-1..k+2
     qa[0] = qb[0] = qc[0] = T(0);
-    qa[1] = ldb(s13, o - 2 * sz);
-    qa[2] = ldb(s13, o - sz);
-    qa[3] = ldb(s13, o);
-    qb[1] = ldb(s23, o - 2 * sz);
-    qb[2] = ldb(s23, o - sz);
-    qb[3] = ldb(s23, o);
-    qc[1] = ldb(s33, o - sz);
-    qc[2] = ldb(s33, o);
-    qc[3] = ldb(s33, o + sz);
+    qa[1] = ld_if(sh, s13, o - 2 * sz);
+    qa[2] = ld_if(sh, s13, o - sz);
+    qa[3] = ld_if(sh, s13, o);
+    qb[1] = ld_if(sh, s23, o - 2 * sz);
+    qb[2] = ld_if(sh, s23, o - sz);
+    qb[3] = ld_if(sh, s23, o);
+    qc[1] = ldb(p33, o - sz);
+    qc[2] = ldb(p33, o);
+    qc[3] = ldb(p33, o + sz);
     T rho_k = ldb(d.rho, o), alp_k = ldb(d.alpha, o);
     for (int k = z0; k < z1; ++k, o += sz) {
 #pragma unroll
@@ -315,18 +344,26 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
             qb[n] = qb[n + 1];
             qc[n] = qc[n + 1];
         }
-        qa[3] = ldb(s13, o + sz);
-        qb[3] = ldb(s23, o + sz);
-        qc[3] = ldb(s33, o + 2 * sz);
-        T a11[4], a12[4], a13[4], b12[4], b22[4], b23[4];   // taps along x (a) and y (b)
+        qc[3] = ldb(p33, o + 2 * sz);
+        T a11[4], a12[4] = {}, a13[4] = {}, b12[4] = {}, b22[4], b23[4] = {};   // taps along x (a) and y (b)
+        T qa3 = T(0), qb3 = T(0);
+        if (sh) {
+            qa3 = ldb(s13, o + sz);
+            qb3 = ldb(s23, o + sz);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                a12[q] = ldb(s12, o + (unsigned)(q - 2) * sx);   // Dm: -2 .. +1
+                a13[q] = ldb(s13, o + (unsigned)(q - 2) * sx);
+                b12[q] = ldb(s12, o + (unsigned)(q - 2) * sy);
+                b23[q] = ldb(s23, o + (unsigned)(q - 2) * sy);
+            }
+        }
+        qa[3] = qa3;
+        qb[3] = qb3;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             a11[q] = ldb(s11, o + (unsigned)(q - 1) * sx);   // Dp: -1 .. +2
-            a12[q] = ldb(s12, o + (unsigned)(q - 2) * sx);   // Dm: -2 .. +1
-            a13[q] = ldb(s13, o + (unsigned)(q - 2) * sx);
-            b12[q] = ldb(s12, o + (unsigned)(q - 2) * sy);
-            b22[q] = ldb(s22, o + (unsigned)(q - 1) * sy);
-            b23[q] = ldb(s23, o + (unsigned)(q - 2) * sy);
+            b22[q] = ldb(p22, o + (unsigned)(q - 1) * sy);
         }
         T uold[3], rho_n[3], alp_n[3];
 #pragma unroll
@@ -562,26 +599,33 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
         else fluid_str<T, ADJ, false>(d, i, j, y0, z0, z1, o, t, edges, false, snx, sny, sox, soy);
         return;
     }
-    if (cols && ((tl.lanes[kTileY * t + (int)threadIdx.x / TX] >> ((int)threadIdx.x % TX)) & 1ull)) {
-        // fluid column of a general tile: its neighbours read s22 and s33, so all are stored
+    bool fl;
+    if (fluid_row(tl, t, x0, d.nx, cols, fl) || (ADJ && fl)) {
+        // fluid row of a general tile (or, in the adjoint, a fluid lane of a mixed row, as in
+        // the velocity pass): its neighbours read s22 and s33, so all are stored
         fluid_str<T, ADJ, false>(d, i, j, y0, z0, z1, o, t, 0, true, snx, sny, sox, soy);
         return;
     }
+    // A fluid lane of a mixed row needs only the normal strains: the shear-strain taps and
+    // the moduli read as zero (their true values on this lane's cell and taps), the shear
+    // stresses are neither read nor written, and s22 = s33 = s11 is read from s11.
+    const bool sh = !fl;
+    const T *p22 = fl ? d.f[S11] : d.f[S22], *p33 = fl ? d.f[S11] : d.f[S33];
     T qa[4], qb[4], qc[4];   // u1, u2 at planes k-1..k+2; u3 at planes k-2..k+1
     qa[0] = qb[0] = qc[0] = T(0);
-    qa[1] = ldb(u1, o - sz);
-    qa[2] = ldb(u1, o);
-    qa[3] = ldb(u1, o + sz);
-    qb[1] = ldb(u2, o - sz);
-    qb[2] = ldb(u2, o);
-    qb[3] = ldb(u2, o + sz);
+    qa[1] = ld_if(sh, u1, o - sz);
+    qa[2] = ld_if(sh, u1, o);
+    qa[3] = ld_if(sh, u1, o + sz);
+    qb[1] = ld_if(sh, u2, o - sz);
+    qb[2] = ld_if(sh, u2, o);
+    qb[3] = ld_if(sh, u2, o + sz);
     qc[1] = ldb(u3, o - 2 * sz);
     qc[2] = ldb(u3, o - sz);
     qc[3] = ldb(u3, o);
     // mu at the cell and its +x, +y neighbours of the current plane, and their reciprocals
     // (carried from the previous plane)
-    T m0 = ldb(d.mu, o);
-    T r0 = rcp(m0), rx = rcp(ldb(d.mu, o + sx)), ry = rcp(ldb(d.mu, o + sy));
+    T m0 = ld_if(sh, d.mu, o);
+    T r0 = rcp(m0), rx = rcp(ld_if(sh, d.mu, o + sx)), ry = rcp(ld_if(sh, d.mu, o + sy));
     for (int k = z0; k < z1; ++k, o += sz) {
 #pragma unroll
         for (int n = 0; n < 3; ++n) {
@@ -589,25 +633,38 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
             qb[n] = qb[n + 1];
             qc[n] = qc[n + 1];
         }
-        qa[3] = ldb(u1, o + 2 * sz);
-        qb[3] = ldb(u2, o + 2 * sz);
         qc[3] = ldb(u3, o + sz);
-        T a1[4], a2[4], a3[4], b1[4], b2[4], b3[4];   // taps along x (a) and y (b)
+        T a1[4], a2[4] = {}, a3[4] = {}, b1[4] = {}, b2[4], b3[4] = {};   // taps along x (a) and y (b)
+        T sold[6] = {};
+        T qa3 = T(0), qb3 = T(0), mz = T(0), mxz = T(0), myz = T(0), mxy = T(0);
+        if (sh) {
+            qa3 = ldb(u1, o + 2 * sz);
+            qb3 = ldb(u2, o + 2 * sz);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                a2[q] = ldb(u2, o + (unsigned)(q - 1) * sx);   // Dp: -1 .. +2
+                a3[q] = ldb(u3, o + (unsigned)(q - 1) * sx);
+                b1[q] = ldb(u1, o + (unsigned)(q - 1) * sy);
+                b3[q] = ldb(u3, o + (unsigned)(q - 1) * sy);
+            }
+#pragma unroll
+            for (int c = 3; c < 6; ++c) sold[c] = ldb(d.f[S11 + c], o);
+            mz = ldb(d.mu, o + sz);
+            mxz = ldb(d.mu, o + sx + sz);
+            myz = ldb(d.mu, o + sy + sz);
+            mxy = ldb(d.mu, o + sx + sy);
+        }
+        qa[3] = qa3;
+        qb[3] = qb3;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             a1[q] = ldb(u1, o + (unsigned)(q - 2) * sx);   // Dm: -2 .. +1
-            a2[q] = ldb(u2, o + (unsigned)(q - 1) * sx);   // Dp: -1 .. +2
-            a3[q] = ldb(u3, o + (unsigned)(q - 1) * sx);
-            b1[q] = ldb(u1, o + (unsigned)(q - 1) * sy);
             b2[q] = ldb(u2, o + (unsigned)(q - 2) * sy);
-            b3[q] = ldb(u3, o + (unsigned)(q - 1) * sy);
         }
-        T sold[6];
-#pragma unroll
-        for (int c = 0; c < 6; ++c) sold[c] = ldb(d.f[S11 + c], o);
+        sold[0] = ldb(d.f[S11], o);
+        sold[1] = ldb(p22, o);
+        sold[2] = ldb(p33, o);
         const T lam = ldb(d.lam, o);
-        const T mz = ldb(d.mu, o + sz), mxz = ldb(d.mu, o + sx + sz), myz = ldb(d.mu, o + sy + sz);
-        const T mxy = ldb(d.mu, o + sx + sy);
         __builtin_amdgcn_sched_barrier(0);
         T e[3][3];   // e[c][a] = D_a In_ca
         e[0][0] = dminus(a1[0], a1[1], a1[2], a1[3], h);
@@ -669,7 +726,11 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
         w[4] = sold[4] + sc * m13 * (e[0][2] + e[2][0]);
         w[5] = sold[5] + sc * m12 * (e[0][1] + e[1][0]);
 #pragma unroll
-        for (int c = 0; c < 6; ++c) stb(d.f[S11 + c], o, w[c]);
+        for (int c = 0; c < 3; ++c) stb(d.f[S11 + c], o, w[c]);
+        if (sh) {
+#pragma unroll
+            for (int c = 3; c < 6; ++c) stb(d.f[S11 + c], o, w[c]);
+        }
         if (ADJ) {
 #pragma unroll
             for (int a = 0; a < 3; ++a) {

@@ -108,6 +108,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="skull384")
     ap.add_argument("--nsteps", type=int, default=0, help="override the trace length M (diagnostics only)")
+    ap.add_argument("--timing-every", type=int, default=10,
+                    help="bracket the kernel launches of every n-th time step with HIP events (1: all)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-sample-steps", type=int, default=3)
     ap.add_argument("--no-serving", action="store_true", help="skip the plain vs batched serving comparison")
@@ -160,7 +162,7 @@ def main():
         torch.cuda.synchronize()
         log(f"[bench] warmup {w + 1}/{args.warmup} done")
 
-    plan.timing(True)
+    plan.timing(True, every=args.timing_every)
     ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
     torch.cuda.synchronize()
     t_start = time.perf_counter()
@@ -199,7 +201,8 @@ def main():
     traffic = measured_traffic(dom, sc.name)
     roofline = {"bound": "hbm", "achieved": d["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": d["gbs"] / HBM_PEAK_GBS, "traffic": traffic, "kernel": dom,
-                "bytes_per_launch": d["bytes_per_launch"], "avg_launch_us": d["avg_us"]}
+                "bytes_per_launch": d["bytes_per_launch"], "avg_launch_us": d["avg_us"],
+                "timed_launches": d["launches"], "timing_every": args.timing_every}
     step_gb = sum(bytemodel.step_bytes(op, sc.nx, sc.ny, sc.nz, sc.npml, sc.nrec, 4, fluid_cells, fluid_layer,
                                        skipped, uniform) for op in ("fwd", "adj")) * (sc.nsteps - 1)
     whole_gbs = step_gb * args.steps / (total_ms / 1e3) / 1e9

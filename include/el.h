@@ -250,14 +250,18 @@ el_status el_plan_fluid_path(el_plan plan, int32_t enable, el_fluid_stats *stats
 #define EL_K_COUNT        6
 
 /*
- * Benchmark instrumentation.  With enable = 1, every kernel launch of the
- * time loops of later el_forward / el_adjoint calls is bracketed by a pair
- * of HIP events recorded on that call's stream; enable = 0 stops recording.
+ * Benchmark instrumentation.  With every = n >= 1, the kernel launches of the
+ * time loops of later el_forward / el_adjoint calls that belong to time steps
+ * m with m mod n = 0 (n = 1: every launch) are each bracketed by a pair of
+ * HIP events recorded on that call's stream; every = 0 stops recording.  An
+ * event between two kernels costs each a few microseconds of issue gap, so a
+ * sample of the steps keeps the timed loop close to its untimed speed.
  * el_plan_kernel_time() waits for the recorded events, returns how many
  * launches of one kind were recorded and their summed duration in ms, and
  * clears the record of that kind.  Host-blocking; not for production loops.
+ * Errors: EL_EINVAL for a NULL plan or a negative every.
  */
-el_status el_plan_timing(el_plan plan, int32_t enable);
+el_status el_plan_timing(el_plan plan, int32_t every);
 el_status el_plan_kernel_time(el_plan plan, int32_t kind, int64_t *launches, double *total_ms);
 
 /*

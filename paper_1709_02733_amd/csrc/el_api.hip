@@ -427,10 +427,10 @@ el_status check_plan(el_plan p) {
     return EL_OK;
 }
 
-// Launch one kernel of the time loops, bracketed by an event pair when timing is on.
+// Launch one kernel of time step m, bracketed by an event pair when timing samples that step.
 template <typename F>
-hipError_t timed(el_plan p, int kind, hipStream_t s, F launch) {
-    if (!p->timing) return launch();
+hipError_t timed(el_plan p, int kind, int m, hipStream_t s, F launch) {
+    if (p->timing_every <= 0 || m % p->timing_every != 0) return launch();
     auto &v = p->ev[kind];
     if (p->used[kind] == v.size()) {
         hipEvent_t a, b;
@@ -453,11 +453,11 @@ el_status run_forward(el_plan p, Dev<T> &d, const T *p0, double *traces, hipStre
     const int M = p->g.nsteps, L = p->nrec;
     HIP_TRY(launch_zero_state(d, s), "zero state");
     HIP_TRY(launch_inject(d, p0, s), "inject");
-    HIP_TRY(timed(p, EL_K_GATHER, s, [&] { return launch_gather(d, p->rec, traces, s); }), "gather");
+    HIP_TRY(timed(p, EL_K_GATHER, 0, s, [&] { return launch_gather(d, p->rec, traces, s); }), "gather");
     for (int m = 1; m < M; ++m) {
-        HIP_TRY(timed(p, EL_K_VELOCITY, s, [&] { return launch_velocity(d, p->tiles, s); }), "velocity pass");
-        HIP_TRY(timed(p, EL_K_STRESS, s, [&] { return launch_stress(d, p->tiles, s); }), "stress pass");
-        HIP_TRY(timed(p, EL_K_GATHER, s, [&] { return launch_gather(d, p->rec, traces + (size_t)m * L, s); }),
+        HIP_TRY(timed(p, EL_K_VELOCITY, m, s, [&] { return launch_velocity(d, p->tiles, s); }), "velocity pass");
+        HIP_TRY(timed(p, EL_K_STRESS, m, s, [&] { return launch_stress(d, p->tiles, s); }), "stress pass");
+        HIP_TRY(timed(p, EL_K_GATHER, m, s, [&] { return launch_gather(d, p->rec, traces + (size_t)m * L, s); }),
                 "gather");
     }
     if (p->fluid_path && p->fast_tiles > 0) HIP_TRY(launch_fluid_fill(d, p->tiles, s), "fluid fill");
@@ -468,13 +468,13 @@ template <typename T>
 el_status run_adjoint(el_plan p, Dev<T> &d, const double *y, T *out, hipStream_t s) {
     const int M = p->g.nsteps, L = p->nrec;
     HIP_TRY(launch_zero_state(d, s), "zero state");
-    HIP_TRY(timed(p, EL_K_SCATTER, s, [&] { return launch_scatter(d, p->rec, y + (size_t)(M - 1) * L, s); }),
+    HIP_TRY(timed(p, EL_K_SCATTER, M - 1, s, [&] { return launch_scatter(d, p->rec, y + (size_t)(M - 1) * L, s); }),
             "scatter");
     for (int m = M - 1; m >= 1; --m) {
-        HIP_TRY(timed(p, EL_K_ADJ_VELOCITY, s, [&] { return launch_adj_velocity(d, p->tiles, s); }),
+        HIP_TRY(timed(p, EL_K_ADJ_VELOCITY, m, s, [&] { return launch_adj_velocity(d, p->tiles, s); }),
                 "adjoint velocity pass");
-        HIP_TRY(timed(p, EL_K_ADJ_STRESS, s, [&] { return launch_adj_stress(d, p->tiles, s); }), "adjoint stress pass");
-        HIP_TRY(timed(p, EL_K_SCATTER, s, [&] { return launch_scatter(d, p->rec, y + (size_t)(m - 1) * L, s); }),
+        HIP_TRY(timed(p, EL_K_ADJ_STRESS, m, s, [&] { return launch_adj_stress(d, p->tiles, s); }), "adjoint stress pass");
+        HIP_TRY(timed(p, EL_K_SCATTER, m - 1, s, [&] { return launch_scatter(d, p->rec, y + (size_t)(m - 1) * L, s); }),
                 "scatter");
     }
     if (p->fluid_path && p->fast_tiles > 0) HIP_TRY(launch_fluid_fill(d, p->tiles, s), "fluid fill");
@@ -642,9 +642,10 @@ el_status el_plan_destroy(el_plan p) {
     return EL_OK;
 }
 
-el_status el_plan_timing(el_plan p, int32_t enable) {
+el_status el_plan_timing(el_plan p, int32_t every) {
     if (!p) return fail(EL_EINVAL, "plan is NULL");
-    p->timing = enable != 0;
+    if (every < 0) return fail(EL_EINVAL, "every must be >= 0");
+    p->timing_every = every;
     return EL_OK;
 }
 

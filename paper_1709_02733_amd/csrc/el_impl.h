@@ -233,7 +233,7 @@ struct el_plan_ {
     hipEvent_t done;
     double cmax;
     // benchmark instrumentation: per kernel kind, event pairs and how many are in use
-    bool timing = false;
+    int timing_every = 0;              // bracket the launches of steps m with m % timing_every == 0
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[EL_K_COUNT];
     size_t used[EL_K_COUNT] = {};
 };

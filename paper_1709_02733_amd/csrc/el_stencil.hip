@@ -317,14 +317,15 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
         return;
     }
     bool fl;
-    if (fluid_row(tl, t, x0, d.nx, cols, fl) || (ADJ && fl)) {
-        // the adjoint's general loop has no registers to spare for the masked loads, so its
-        // fluid lanes of a mixed row run the fluid loop (the row executes both loops)
+    if (fluid_row(tl, t, x0, d.nx, cols, fl)) {
         fluid_vel<T, ADJ, false>(d, i, j, z0, z1, o, t, snx, sny, sox, soy);
         return;
     }
     const bool sh = !fl;                     // this lane reads the shear stresses
-    const T *p22 = fl ? s11 : s22, *p33 = fl ? s11 : s33;
+    // s22 and s33 hold s11's value on a fluid lane's taps (fluid columns store all three,
+    // fluid tiles the bands next to general tiles); the forward pass reads them from s11,
+    // the adjoint, with no registers to spare for per-lane pointers, from their own arrays
+    const T *p22 = fl && !ADJ ? s11 : s22, *p33 = fl && !ADJ ? s11 : s33;
     T qa[4], qb[4], qc[4];   // s13, s23 at planes k-2..k+1; s33 at planes k-1..k+2
     qa[0] = qb[0] = qc[0] = T(0);
     qa[1] = ld_if(sh, s13, o - 2 * sz);
@@ -601,8 +602,9 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
     }
     bool fl;
     if (fluid_row(tl, t, x0, d.nx, cols, fl) || (ADJ && fl)) {
-        // fluid row of a general tile (or, in the adjoint, a fluid lane of a mixed row, as in
-        // the velocity pass): its neighbours read s22 and s33, so all are stored
+        // fluid row of a general tile (or, in the adjoint, whose general loop has no registers
+        // to spare for the masked loads, a fluid lane of a mixed row; the row then executes
+        // both loops): its neighbours read s22 and s33, so all are stored
         fluid_str<T, ADJ, false>(d, i, j, y0, z0, z1, o, t, 0, true, snx, sny, sox, soy);
         return;
     }

@@ -189,6 +189,7 @@ class Plan:
                                   ctypes.c_void_p(self.workspace.data_ptr()), self.bytes, _stream(stream))
             _check(st)
         self._h = h
+        self._lib = lib()
 
     @classmethod
     def from_scenario(cls, sc, precision="f32", **kw):
@@ -198,7 +199,7 @@ class Plan:
     def close(self):
         h = getattr(self, "_h", None)
         if h is not None and h.value:
-            lib().el_plan_destroy(h)
+            self._lib.el_plan_destroy(h)   # the library handle outlives module teardown
         self._h = None
 
     __del__ = close
@@ -257,9 +258,10 @@ class Plan:
         _check(lib().el_plan_fluid_path(self._h, flag, ctypes.byref(st)))
         return {name: int(getattr(st, name)) for name, _ in FluidStats._fields_}
 
-    def timing(self, enable: bool = True):
-        """Record an event pair around every time-loop kernel launch of later operations."""
-        _check(lib().el_plan_timing(self._h, 1 if enable else 0))
+    def timing(self, enable: bool = True, every: int = 1):
+        """Record an event pair around the time-loop kernel launches of every `every`-th time
+        step of later operations (el_plan_timing); enable=False stops recording."""
+        _check(lib().el_plan_timing(self._h, int(every) if enable else 0))
 
     def kernel_times(self) -> dict:
         """{kernel: (launches, total_ms)} recorded since the last call (host-blocking)."""
@@ -332,6 +334,7 @@ class Executor:
         with torch.cuda.device(self.device):
             _check(lib().el_exec_create(ctypes.byref(h), int(max_slots), int(chunk)))
         self._h = h
+        self._lib = lib()
         self.max_slots = int(max_slots)
         self._held = {}
 
@@ -365,7 +368,7 @@ class Executor:
         h = getattr(self, "_h", None)
         if h is not None and h.value:
             with torch.cuda.device(self.device):
-                lib().el_exec_destroy(h)
+                self._lib.el_exec_destroy(h)   # the library handle outlives module teardown
         self._h = None
         self._held = {}
 

@@ -126,6 +126,32 @@ def test_forward_is_deterministic():
     assert torch.equal(plan.adjoint(y).clone(), plan.adjoint(y).clone())
 
 
+@pytest.mark.parametrize("every", [1, 3])
+def test_kernel_timing_samples_steps(every):
+    """el_plan_timing(every): event pairs bracket the launches of time steps m with
+    m mod every = 0; results are those of an untimed run."""
+    sc = S.random_scenario((23, 19, 17), seed=5, nsteps=11, npml=2, nrec=6)
+    plan = el.Plan.from_scenario(sc)
+    p = torch.from_numpy(sc.p0)
+    y = torch.randn(sc.nsteps, sc.nrec, dtype=torch.float64, generator=torch.Generator().manual_seed(1))
+    tr0 = plan.forward(p).cpu()
+    pa0 = plan.adjoint(y).cpu()
+    plan.timing(True, every=every)
+    tr = plan.forward(p).cpu()
+    pa = plan.adjoint(y).cpu()
+    plan.timing(False)
+    kt = plan.kernel_times()
+    M = sc.nsteps
+    steps = [m for m in range(1, M) if m % every == 0]        # stencil passes run for m = 1 .. M-1
+    rows = [m for m in range(0, M) if m % every == 0]         # one gather / scatter per trace row
+    assert kt["velocity"][0] == kt["stress"][0] == len(steps)
+    assert kt["adj_velocity"][0] == kt["adj_stress"][0] == len(steps)
+    assert kt["gather"][0] == kt["scatter"][0] == len(rows)
+    assert all(ms > 0 for n, ms in kt.values() if n)
+    assert torch.equal(tr, tr0) and torch.equal(pa, pa0)
+    assert all(n == 0 for n, _ in plan.kernel_times().values())   # the record was cleared
+
+
 def test_negative_zero_shear_modulus():
     """A fluid cell given as mu = -0.0 behaves as mu = +0.0: the staggered harmonic means
     of the shear modulus are zero next to it (Sec. 2.2), results match the oracle and are

@@ -149,7 +149,7 @@ def main():
     skipped, uniform = fl["skipped_stores"], fl["uniform_cells"]
     log(f"[bench] fluid tiles: {fl['tiles']} ({fluid_cells / sc.ncells:.1%} of the cells take the fluid update; "
         f"{fluid_layer} fluid C-PML cell-axis pairs; {skipped} s22/s33 stores left out per stress pass; "
-        f"{uniform / sc.ncells:.1%} of the cells in uniform fluid tiles)")
+        f"{uniform / sc.ncells:.1%} of the cells take lambda, rho, alpha from the per-tile table)")
     dev = plan.device
     p0 = torch.from_numpy(sc.p0).to(dev)
     traces = torch.empty((sc.nsteps, sc.nrec), dtype=torch.float64, device=dev)

@@ -215,7 +215,9 @@ el_status el_plan_sizes(el_plan plan, int64_t *ncells, int32_t *nrec, int32_t *n
  * a per-tile table instead of the maps, again with the same results.
  * Inside the other tiles, every column of 1 x 1 cells by the chunk whose
  * cells within two have mu = 0 is marked too, and its lanes run the same
- * fluid update (storing all three normal stresses).
+ * fluid update (storing all three normal stresses); a column whose box holds
+ * the tile's reference medium (that of its first fluid column) takes it from
+ * the table as well.
  */
 typedef struct el_fluid_stats {
     int64_t tiles;           /* tiles that take the fluid update                   */
@@ -225,8 +227,9 @@ typedef struct el_fluid_stats {
                              /* memory variable is carried there                   */
     int64_t skipped_stores;  /* s22 and s33 stores (cell, component pairs) one     */
                              /* stress pass leaves out                             */
-    int64_t uniform_cells;   /* cells of fluid tiles with uniform lambda, rho,     */
-                             /* alpha (maps not read)                              */
+    int64_t uniform_cells;   /* fluid-update cells whose lambda, rho, alpha come   */
+                             /* from the per-tile table: uniform fluid tiles, and  */
+                             /* fluid columns of their tile's reference medium     */
     int64_t column_cells;    /* cells of fluid columns inside other tiles          */
 } el_fluid_stats;
 

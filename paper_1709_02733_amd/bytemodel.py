@@ -21,8 +21,9 @@ s22 = s33 = s11 and the shear stresses are zero:
   stress / adj_stress      reads u x3, s11, lambda;     writes s11, s22, s33      ->  8 es
 less one element for every s22 or s33 store the stress passes leave out (those
 stresses are stored only where a general-update tile reads them, el_plan_fluid_path),
-less rho and alpha (velocity) or lambda (stress) on a fluid tile of uniform media, whose
-values come from a per-tile table,
+less rho and alpha (velocity) or lambda (stress) on a fluid cell of uniform media, whose
+values come from a per-tile table (the algorithm's bytes: where a kernel still reads a map
+it does not need, that read counts as traffic above the model),
 and per fluid cell of each axis's C-PML layers only the diagonal memory variable:
   velocity / stress        phi^aa (psi^aa) read + written                        ->  2 es
   adj_velocity / adj_stress a psi~^aa (a phi~^aa) read, a phi~^aa (a psi~^aa) read + written -> 3 es

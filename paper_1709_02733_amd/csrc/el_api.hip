@@ -101,7 +101,7 @@ bool layout(const el_grid &g, int nrec, Layout *L) {
         L->tile_order = take((size_t)8 * t.per * sizeof(int));
         L->tile_flags = take(2 * (size_t)t.ntiles);
         L->tile_media = take((size_t)4 * t.ntiles * es);
-        L->tile_lanes = take((size_t)kTileY * t.ntiles * 8);
+        L->tile_lanes = take((size_t)2 * kTileY * t.ntiles * 8);
     }
     L->partial = take(7 * kDotBlocks * 8);
     L->total = off;
@@ -566,7 +566,7 @@ el_status el_plan_create(el_plan *out, const el_grid *grid, const float *lam, co
         p->fast.assign(p->tiles.ntiles, 0);
         p->uni.assign(p->tiles.ntiles, 0);
         p->cols.assign(p->tiles.ntiles, 0);
-        std::vector<unsigned long long> hl((size_t)kTileY * p->tiles.ntiles, 0);
+        std::vector<unsigned long long> hl((size_t)2 * kTileY * p->tiles.ntiles, 0);
         if (e == hipSuccess && p->tiles.ntiles > 0)
             e = hipMemcpyAsync(hl.data(), lanes, hl.size() * 8, hipMemcpyDeviceToHost, s);
         if (e == hipSuccess && p->tiles.ntiles > 0)
@@ -594,6 +594,8 @@ el_status el_plan_create(el_plan *out, const el_grid *grid, const float *lam, co
                     const unsigned long long m = hl[(size_t)kTileY * q + row];
                     if (!m) continue;
                     p->cols[q] = 1;
+                    const unsigned long long um = hl[(size_t)kTileY * ((size_t)t.ntiles + q) + row];
+                    p->uniform_cells += (long long)__builtin_popcountll(um) * dep;
                     for (int b = 0; b < 64; ++b) {
                         if (!((m >> b) & 1ull)) continue;
                         const int i = bx * kTileX + b, j = by * kTileY + row;

@@ -115,7 +115,8 @@ struct Tiles {
     int ntiles;              // ntx * nty * nzc
     int per;                 // tiles per XCD: the grid has 8 * per blocks
     const int *order;        // device: tile of each block (-1 for a padding block)
-    const unsigned long long *lanes;   // device: per tile and row, its fluid columns (k_classify)
+    const unsigned long long *lanes;   // device: per tile and row, its fluid columns; then, per tile
+                                       // and row, those of the tile's reference medium (k_classify)
 };
 Tiles make_tiles(int nx, int ny, int nz);
 // XCD (0..7) that processes tile q; blocks run on XCD blockIdx % 8.
@@ -169,7 +170,7 @@ struct Layout {
     size_t tile_order;       // tile of each stencil block
     size_t tile_flags;       // per tile: 1 if the fluid update applies; then per tile: 1 if uniform
     size_t tile_media;       // per tile: lambda, rho, alpha, 0 (elements of the plan's precision)
-    size_t tile_lanes;       // per tile and row: 64-bit mask of fluid columns
+    size_t tile_lanes;       // per tile and row: 64-bit masks of fluid columns, then of uniform ones
     size_t partial;          // reduction partials
     size_t total;
 };

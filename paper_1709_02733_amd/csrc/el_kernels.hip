@@ -144,7 +144,10 @@ hipError_t launch_zero_state(const Dev<T> &d, hipStream_t s) {
 // Inside a tile that is not fluid, column (i, j) of its chunk is fluid when mu = 0 on the
 // cells within two of it (x, y in [i-2, i+2] x [j-2, j+2], z from z0-2 to z1+1, clipped to
 // the grid): bit i-x0 of lanes[4 q + j-y0], set for such columns, lets the lanes of those
-// columns run the fluid update inside the general tile.
+// columns run the fluid update inside the general tile.  The tile's first fluid column (in
+// row-major lane order) gives a reference medium, written to med[4 q + 0..2]; bit i-x0 of
+// lanes[4 ntiles + 4 q + j-y0] marks the fluid columns whose lambda, rho and alpha equal the
+// reference bit for bit on that same box, which then take them from the table.
 //
 // A fluid tile whose lambda, rho and alpha are each one value (bit for bit) over the same
 // box is also marked uniform, and its three values are written to med[4 q + 0..2]: the
@@ -209,13 +212,57 @@ __global__ __launch_bounds__(kTileX * kTileY) void k_classify(Dev<T> d, Tiles tl
                 if (col_solid[(ly + dy) * HX + lx + dx]) colfluid = 0;
     }
     const unsigned long long m = __ballot(colfluid);
-    if ((threadIdx.x & 63) == 0) lanes[4 * (size_t)q + threadIdx.x / 64] = m;
+    __shared__ unsigned long long rowm[kTileY];
+    __shared__ T ref[3];
+    if ((threadIdx.x & 63) == 0) {
+        lanes[4 * (size_t)q + threadIdx.x / 64] = m;
+        rowm[threadIdx.x / 64] = m;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        // reference medium: the first fluid column's cell of plane z0, else the box corner's
+        T rl = l0, rr = r0, ra = a0;
+        for (int row = 0; row < kTileY; ++row)
+            if (rowm[row]) {
+                const int lane = __ffsll((long long)rowm[row]) - 1;
+                const long long c = (long long)(z0 + 2) * d.plane + (long long)(y0 + row) * d.px + x0 + lane;
+                rl = d.lam[c];
+                rr = d.rho[c];
+                ra = d.alpha[c];
+                break;
+            }
+        ref[0] = rl;
+        ref[1] = rr;
+        ref[2] = ra;
+    }
+    __syncthreads();
+    // columns of the tile and two around it: are lambda, rho, alpha the reference's from z0-2
+    // to z1+1?  (Columns outside the grid hold nothing the loops read.)
+    __shared__ unsigned char col_vary[HX * HY];
+    for (int e = threadIdx.x; e < HX * HY; e += blockDim.x) {
+        const int xx = x0 - 2 + e % HX, yy = y0 - 2 + e / HX;
+        int v = 0;
+        if (xx >= 0 && xx < d.nx && yy >= 0 && yy < d.ny)
+            for (int zz = az; zz < min(z1 + 2, d.nz); ++zz) {
+                const long long c = (long long)(zz + 2) * d.plane + (long long)yy * d.px + xx;
+                if (!same_bits(d.lam[c], ref[0]) || !same_bits(d.rho[c], ref[1]) || !same_bits(d.alpha[c], ref[2])) v = 1;
+            }
+        col_vary[e] = (unsigned char)v;
+    }
+    __syncthreads();
+    int colunif = colfluid;
+    for (int dy = 0; dy < 5 && colunif; ++dy)
+        for (int dx = 0; dx < 5; ++dx)
+            if (col_vary[(ly + dy) * HX + lx + dx]) colunif = 0;
+    const unsigned long long um = __ballot(colunif);
+    if ((threadIdx.x & 63) == 0) lanes[4 * ((size_t)tl.ntiles + q) + threadIdx.x / 64] = um;
     if (threadIdx.x == 0) {
         fast[q] = solid ? 0 : 1;
         uni[q] = solid || vary ? 0 : 1;
-        med[4 * (size_t)q + 0] = l0;
-        med[4 * (size_t)q + 1] = r0;
-        med[4 * (size_t)q + 2] = a0;
+        // a fluid tile keeps its box corner's values (every cell's, when it is uniform)
+        med[4 * (size_t)q + 0] = solid ? ref[0] : l0;
+        med[4 * (size_t)q + 1] = solid ? ref[1] : r0;
+        med[4 * (size_t)q + 2] = solid ? ref[2] : a0;
         med[4 * (size_t)q + 3] = T(0);
     }
 }

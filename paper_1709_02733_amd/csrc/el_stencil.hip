@@ -73,20 +73,32 @@ __device__ __forceinline__ T ld_if(bool on, const T *base, unsigned off) {
     if (on) v = ldb(base, off);
     return v;
 }
+// Load unless off (then alt), under the lane mask likewise.
+template <typename T>
+__device__ __forceinline__ T ld_or(bool on, const T *base, unsigned off, T alt) {
+    T v = alt;
+    if (on) v = ldb(base, off);
+    return v;
+}
 
-// Fluid columns of a general tile (Tiles::lanes).  A row whose columns are all fluid runs
-// the fluid loop (returns true after doing so); in a mixed row the fluid lanes run the
-// general loop with *fl set: the loads they do not need are masked off (their shear taps
-// are zero, and s22 = s33 = s11 on their taps, so those taps are read from s11).
-__device__ __forceinline__ bool fluid_row(const Tiles &tl, int t, int x0, int nx, bool cols, bool &fl) {
-    fl = false;
+// Fluid columns of a general tile (Tiles::lanes).  fl: this lane's column is fluid; ul: its
+// lambda, rho and alpha are the tile's reference medium (in the per-tile table).  Returns
+// true for a row whose columns are all fluid, which runs the fluid loop (uniform when every
+// column is, rowuni); in a mixed row the fluid lanes run the general loop with the loads they
+// do not need masked off (their shear taps are zero, and s22 = s33 = s11 on their taps).
+__device__ __forceinline__ bool fluid_row(const Tiles &tl, int t, int x0, int nx, bool cols, bool &fl, bool &ul,
+                                          bool &rowuni) {
+    fl = ul = rowuni = false;
     if (!cols) return false;
-    const unsigned long long m = tl.lanes[kTileY * t + (int)threadIdx.x / TX];
+    const int row = (int)threadIdx.x / TX, lane = (int)threadIdx.x % TX;
+    const unsigned long long m = tl.lanes[kTileY * t + row];
+    const unsigned long long um = tl.lanes[kTileY * ((size_t)tl.ntiles + t) + row];
     const int nv = min(TX, nx - x0);
     const unsigned long long valid = nv >= 64 ? ~0ull : ((1ull << nv) - 1ull);
-    if (m == valid) return true;
-    fl = ((m >> ((int)threadIdx.x % TX)) & 1ull) != 0;
-    return false;
+    fl = ((m >> lane) & 1ull) != 0;
+    ul = ((um >> lane) & 1ull) != 0;
+    rowuni = (um & valid) == valid;
+    return (m & valid) == valid;
 }
 
 // 4th-order staggered differences (Sec. 2.2, eq. derivative):
@@ -316,12 +328,16 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
         else fluid_vel<T, ADJ, false>(d, i, j, z0, z1, o, t, snx, sny, sox, soy);
         return;
     }
-    bool fl;
-    if (fluid_row(tl, t, x0, d.nx, cols, fl)) {
-        fluid_vel<T, ADJ, false>(d, i, j, z0, z1, o, t, snx, sny, sox, soy);
+    bool fl, ul, rowuni;
+    if (fluid_row(tl, t, x0, d.nx, cols, fl, ul, rowuni)) {
+        if (rowuni) fluid_vel<T, ADJ, true>(d, i, j, z0, z1, o, t, snx, sny, sox, soy);
+        else fluid_vel<T, ADJ, false>(d, i, j, z0, z1, o, t, snx, sny, sox, soy);
         return;
     }
     const bool sh = !fl;                     // this lane reads the shear stresses
+    const bool mp = ADJ || !ul;              // this lane reads rho and alpha from the maps (the
+                                             // adjoint has no registers to spare for the choice)
+    const T rho_t = d.med[4 * t + 1], alp_t = d.med[4 * t + 2];
     // s22 and s33 hold s11's value on a fluid lane's taps (fluid columns store all three,
     // fluid tiles the bands next to general tiles); the forward pass reads them from s11,
     // the adjoint, with no registers to spare for per-lane pointers, from their own arrays
@@ -337,7 +353,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
     qc[1] = ldb(p33, o - sz);
     qc[2] = ldb(p33, o);
     qc[3] = ldb(p33, o + sz);
-    T rho_k = ldb(d.rho, o), alp_k = ldb(d.alpha, o);
+    T rho_k = ld_or(mp, d.rho, o, rho_t), alp_k = ld_or(mp, d.alpha, o, alp_t);
     for (int k = z0; k < z1; ++k, o += sz) {
 #pragma unroll
         for (int n = 0; n < 3; ++n) {
@@ -369,12 +385,12 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
         T uold[3], rho_n[3], alp_n[3];
 #pragma unroll
         for (int c = 0; c < 3; ++c) uold[c] = ldb(d.f[U1 + c], o);
-        rho_n[0] = ldb(d.rho, o + sx);
-        rho_n[1] = ldb(d.rho, o + sy);
-        rho_n[2] = ldb(d.rho, o + sz);
-        alp_n[0] = ldb(d.alpha, o + sx);
-        alp_n[1] = ldb(d.alpha, o + sy);
-        alp_n[2] = ldb(d.alpha, o + sz);
+        rho_n[0] = ld_or(mp, d.rho, o + sx, rho_t);
+        rho_n[1] = ld_or(mp, d.rho, o + sy, rho_t);
+        rho_n[2] = ld_or(mp, d.rho, o + sz, rho_t);
+        alp_n[0] = ld_or(mp, d.alpha, o + sx, alp_t);
+        alp_n[1] = ld_or(mp, d.alpha, o + sy, alp_t);
+        alp_n[2] = ld_or(mp, d.alpha, o + sz, alp_t);
         __builtin_amdgcn_sched_barrier(0);
         T dd[3][3];
         dd[0][0] = dplus(a11[0], a11[1], a11[2], a11[3], h);
@@ -462,8 +478,9 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
 //   axis x: c=0 Dm, c=1 Dp, c=2 Dp;  axis y: c=0 Dp, c=1 Dm, c=2 Dp;  axis z: c=0 Dp, c=1 Dp, c=2 Dm
 // ------------------------------------------------------------------------
 // Fluid-tile loop of the stress-shaped pass.  UNI: a uniform tile, whose lambda comes from
-// the per-tile table instead of the map (the same value, so the same results).  keep: store
-// s22 and s33 on every cell (a fluid column of a general tile), else only on the bands.
+// the per-tile table instead of the map (the same value, so the same results); ul: the same
+// for this lane alone (a fluid column of the tile's reference medium).  keep: store s22 and
+// s33 on every cell (a fluid column of a general tile), else only on the bands.
 //
 // fluid tile: mu = 0, so the three normal stresses take the same increment lambda tr and
 // the shear stresses stay zero (not written).  Only the diagonal C-PML memory variables
@@ -472,12 +489,12 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
 // the own-point memory variable of a cell are read and written by its own lane only.
 template <typename T, bool ADJ, bool UNI>
 __device__ __forceinline__ void fluid_str(const Dev<T> &d, int i, int j, int y0, int z0, int z1, unsigned o,
-                                          int t, int edges, bool keep, int snx, int sny, int sox, int soy) {
+                                          int t, int edges, bool keep, bool ul, int snx, int sny, int sox, int soy) {
     const T h = d.inv_dx, dt = d.dt;
     const unsigned sx = sizeof(T), sy = d.sy, sz = d.sz;
     const T *u1 = d.f[U1], *u2 = d.f[U2], *u3 = d.f[U3];
     const bool pml = d.P > 0;
-    const T lam_t = UNI ? d.med[4 * t] : T(0);
+    const T lam_t = d.med[4 * t];
     // s22 is stored on the rows, s33 on the planes, that general tiles read across a face
     const bool put22 = keep || ((edges & 1) && j < y0 + 2) || ((edges & 2) && j >= y0 + TY - 2);
     const int zlo = keep ? z1 : ((edges & 4) ? z0 + 2 : z0), zhi = keep ? z0 : ((edges & 8) ? z1 - 2 : z1);
@@ -504,7 +521,7 @@ __device__ __forceinline__ void fluid_str(const Dev<T> &d, int i, int j, int y0,
             p.b2[q] = ldb(u2, oo + (unsigned)(q - 2) * sy);
         }
         p.sold = ldb(d.f[S11], oo);
-        p.lam = UNI ? lam_t : ldb(d.lam, oo);
+        p.lam = UNI ? lam_t : ld_or(!ul, d.lam, oo, lam_t);
         p.so_z = pml ? slab_own(kk, d.P, d.hi[2]) : -1;
         p.sn_z = ADJ && pml ? slab_near(kk, d.P, d.hi[2]) : -1;
         p.pa_z = p.so_z >= 0 ? d.pa[2][0][kk] : T(0);
@@ -596,16 +613,18 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
     const int snx = pml ? slab_near(i, d.P, d.hi[0]) : -1, sny = pml ? slab_near(j, d.P, d.hi[1]) : -1;
     const int sox = pml ? slab_own(i, d.P, d.hi[0]) : -1, soy = pml ? slab_own(j, d.P, d.hi[1]) : -1;
     if (fast) {
-        if (uni) fluid_str<T, ADJ, true>(d, i, j, y0, z0, z1, o, t, edges, false, snx, sny, sox, soy);
-        else fluid_str<T, ADJ, false>(d, i, j, y0, z0, z1, o, t, edges, false, snx, sny, sox, soy);
+        if (uni) fluid_str<T, ADJ, true>(d, i, j, y0, z0, z1, o, t, edges, false, true, snx, sny, sox, soy);
+        else fluid_str<T, ADJ, false>(d, i, j, y0, z0, z1, o, t, edges, false, false, snx, sny, sox, soy);
         return;
     }
-    bool fl;
-    if (fluid_row(tl, t, x0, d.nx, cols, fl) || (ADJ && fl)) {
+    bool fl, ul, rowuni;
+    const bool row = fluid_row(tl, t, x0, d.nx, cols, fl, ul, rowuni);
+    if (row || (ADJ && fl)) {
         // fluid row of a general tile (or, in the adjoint, whose general loop has no registers
         // to spare for the masked loads, a fluid lane of a mixed row; the row then executes
         // both loops): its neighbours read s22 and s33, so all are stored
-        fluid_str<T, ADJ, false>(d, i, j, y0, z0, z1, o, t, 0, true, snx, sny, sox, soy);
+        if (row && rowuni) fluid_str<T, ADJ, true>(d, i, j, y0, z0, z1, o, t, 0, true, true, snx, sny, sox, soy);
+        else fluid_str<T, ADJ, false>(d, i, j, y0, z0, z1, o, t, 0, true, ul, snx, sny, sox, soy);
         return;
     }
     // A fluid lane of a mixed row needs only the normal strains: the shear-strain taps and
@@ -613,6 +632,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
     // stresses are neither read nor written, and s22 = s33 = s11 is read from s11.
     const bool sh = !fl;
     const T *p22 = fl ? d.f[S11] : d.f[S22], *p33 = fl ? d.f[S11] : d.f[S33];
+    const T lam_t = d.med[4 * t];   // lambda of the tile's reference medium (lanes with ul)
     T qa[4], qb[4], qc[4];   // u1, u2 at planes k-1..k+2; u3 at planes k-2..k+1
     qa[0] = qb[0] = qc[0] = T(0);
     qa[1] = ld_if(sh, u1, o - sz);
@@ -666,7 +686,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
         sold[0] = ldb(d.f[S11], o);
         sold[1] = ldb(p22, o);
         sold[2] = ldb(p33, o);
-        const T lam = ldb(d.lam, o);
+        const T lam = ld_or(ADJ || !ul, d.lam, o, lam_t);
         __builtin_amdgcn_sched_barrier(0);
         T e[3][3];   // e[c][a] = D_a In_ca
         e[0][0] = dminus(a1[0], a1[1], a1[2], a1[3], h);

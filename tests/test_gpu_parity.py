@@ -235,6 +235,42 @@ def test_fluid_tiles_match_general_update_and_oracle(precision, tol_same, tol_re
     assert rel_l2(pa_fast, ref.adjoint(y)) <= tol_ref
 
 
+def test_fluid_path_ragged_grid():
+    """A 150 x 37 x 29 grid (partial last tiles in x, y and z) of homogeneous water holding a
+    solid ball near the +x face: fluid tiles, fluid rows and mixed rows of partial tiles all
+    occur; the fluid path equals the general update and the oracle."""
+    nx, ny, nz = 150, 37, 29
+    sc = S.random_scenario((nx, ny, nz), seed=21, nsteps=50, npml=3, nrec=12, fluid_fraction=1.0)
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    ball = (x - 138) ** 2 + (y - 18) ** 2 + (z - 14) ** 2 <= 25
+    cp, cs, rho = 2800.0, 1500.0, 1850.0
+    sc.lam = np.where(ball, rho * (cp * cp - 2 * cs * cs), 1000.0 * 1500.0 ** 2).astype(np.float32)
+    sc.mu = np.where(ball, rho * cs * cs, 0.0).astype(np.float32)
+    sc.rho = np.where(ball, rho, 1000.0).astype(np.float32)
+    sc.alpha = np.where(ball, 2.0e5, 1.0e5).astype(np.float32)
+    sc.dt = 0.3 * sc.dx / cp
+    plan = el.Plan.from_scenario(sc)
+    st = plan.fluid_stats()
+    banner(f"ragged fluid path: {st}")
+    assert 0 < st["column_cells"] and 0 < st["uniform_cells"] and st["cells"] < sc.ncells
+    p = torch.from_numpy(sc.p0)
+    y = np.random.default_rng(4).standard_normal((sc.nsteps, sc.nrec))
+    tr_f = plan.forward(p).cpu().numpy()
+    s_f = {f: plan.field(f).cpu().numpy().astype(np.float64) for f in el.FIELDS}
+    pa_f = plan.adjoint(torch.from_numpy(y)).cpu().numpy().astype(np.float64)
+    plan.fluid_path(False)
+    tr_g = plan.forward(p).cpu().numpy()
+    s_g = {f: plan.field(f).cpu().numpy().astype(np.float64) for f in el.FIELDS}
+    pa_g = plan.adjoint(torch.from_numpy(y)).cpu().numpy().astype(np.float64)
+    assert rel_max(tr_f, tr_g) <= 1e-6 and rel_max(pa_f, pa_g) <= 1e-6
+    for name in el.FIELDS:
+        scale = max(np.abs(s_g[name]).max(), np.abs(s_g["s11"]).max())
+        assert np.abs(s_f[name] - s_g[name]).max() / scale <= 1e-6, name
+    ref = Model.from_scenario(sc)
+    assert rel_l2(tr_f, ref.forward(sc.p0.astype(np.float64))) <= TOL32
+    assert rel_l2(pa_f, ref.adjoint(y)) <= TOL32
+
+
 def test_fluid_tiles_dot_product():
     sc = _fluid_ball_scenario(seed=14, nsteps=80)
     plan = el.Plan.from_scenario(sc)

@@ -143,10 +143,10 @@ hipError_t launch_zero_state(const Dev<T> &d, hipStream_t s) {
 //
 // Inside a tile that is not fluid, column (i, j) of its chunk is fluid when mu = 0 on the
 // cells within two of it (x, y in [i-2, i+2] x [j-2, j+2], z from z0-2 to z1+1, clipped to
-// the grid): bit i-x0 of lanes[4 q + j-y0], set for such columns, lets the lanes of those
+// the grid): bit i-x0 of lanes[kTileY q + j-y0], set for such columns, lets the lanes of those
 // columns run the fluid update inside the general tile.  The tile's first fluid column (in
 // row-major lane order) gives a reference medium, written to med[4 q + 0..2]; bit i-x0 of
-// lanes[4 ntiles + 4 q + j-y0] marks the fluid columns whose lambda, rho and alpha equal the
+// lanes[kTileY (ntiles + q) + j-y0] marks the fluid columns whose lambda, rho and alpha equal the
 // reference bit for bit on that same box, which then take them from the table.
 //
 // A fluid tile whose lambda, rho and alpha are each one value (bit for bit) over the same
@@ -215,7 +215,7 @@ __global__ __launch_bounds__(kTileX * kTileY) void k_classify(Dev<T> d, Tiles tl
     __shared__ unsigned long long rowm[kTileY];
     __shared__ T ref[3];
     if ((threadIdx.x & 63) == 0) {
-        lanes[4 * (size_t)q + threadIdx.x / 64] = m;
+        lanes[kTileY * (size_t)q + threadIdx.x / 64] = m;
         rowm[threadIdx.x / 64] = m;
     }
     __syncthreads();
@@ -255,7 +255,7 @@ __global__ __launch_bounds__(kTileX * kTileY) void k_classify(Dev<T> d, Tiles tl
         for (int dx = 0; dx < 5; ++dx)
             if (col_vary[(ly + dy) * HX + lx + dx]) colunif = 0;
     const unsigned long long um = __ballot(colunif);
-    if ((threadIdx.x & 63) == 0) lanes[4 * ((size_t)tl.ntiles + q) + threadIdx.x / 64] = um;
+    if ((threadIdx.x & 63) == 0) lanes[kTileY * ((size_t)tl.ntiles + q) + threadIdx.x / 64] = um;
     if (threadIdx.x == 0) {
         fast[q] = solid ? 0 : 1;
         uni[q] = solid || vary ? 0 : 1;

@@ -47,7 +47,11 @@
 // stores s22 only on two-row bands along y faces shared with general tiles and
 // s33 only on two-plane bands along such z faces (edge bits of the order
 // entry), s11 everywhere; k_fluid_fill restores s22 = s33 = s11 on fluid tiles
-// at the end of an operation.  The results are those of the general loop.
+// at the end of an operation.  Fluid tiles of uniform media take lambda, rho
+// and alpha from a per-tile table.  Inside the other tiles, fluid columns are
+// marked per lane: a row of fluid columns runs the lean loop, and the fluid
+// lanes of a mixed row run the general loop with the loads they do not need
+// masked off.  The results are those of the general loop.
 #include "el_impl.h"
 
 namespace el {

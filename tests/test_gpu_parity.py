@@ -235,12 +235,13 @@ def test_fluid_tiles_match_general_update_and_oracle(precision, tol_same, tol_re
     assert rel_l2(pa_fast, ref.adjoint(y)) <= tol_ref
 
 
-def test_fluid_path_ragged_grid():
+@pytest.mark.parametrize("npml", [0, 3])
+def test_fluid_path_ragged_grid(npml):
     """A 150 x 37 x 29 grid (partial last tiles in x, y and z) of homogeneous water holding a
     solid ball near the +x face: fluid tiles, fluid rows and mixed rows of partial tiles all
-    occur; the fluid path equals the general update and the oracle."""
+    occur; the fluid path equals the general update and the oracle, with and without C-PML."""
     nx, ny, nz = 150, 37, 29
-    sc = S.random_scenario((nx, ny, nz), seed=21, nsteps=50, npml=3, nrec=12, fluid_fraction=1.0)
+    sc = S.random_scenario((nx, ny, nz), seed=21, nsteps=50, npml=npml, nrec=12, fluid_fraction=1.0)
     z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
     ball = (x - 138) ** 2 + (y - 18) ** 2 + (z - 14) ** 2 <= 25
     cp, cs, rho = 2800.0, 1500.0, 1850.0

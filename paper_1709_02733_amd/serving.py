@@ -51,6 +51,8 @@ class Request:
     done: float | None = None
     rejected: bool = False
     output: object = None
+    cancel_at: float | None = None   # the client withdraws the request at this time (run_batched)
+    cancelled: bool = False
 
     @property
     def cell_updates(self) -> int:
@@ -74,7 +76,7 @@ def request_mix(count: int, rate: float, seed: int = 0, sizes=SIZES, fwd_fractio
 
 
 def clone_requests(reqs):
-    return [dataclasses.replace(r, admitted=None, done=None, rejected=False, output=None) for r in reqs]
+    return [dataclasses.replace(r, admitted=None, done=None, rejected=False, output=None, cancelled=False) for r in reqs]
 
 
 class Workloads:
@@ -163,8 +165,12 @@ def run_batched(reqs, wl, executor, budget_bytes: float = 200e9, clock=time.perf
 
     Admission is first come, first served: the oldest arrived request is admitted
     once a slot is free and its footprint fits next to the admitted ones; a request
-    whose footprint alone exceeds the budget is rejected.  `trace`, if given,
-    receives (time, bytes in use, active count) after every change.
+    whose footprint alone exceeds the budget is rejected.  A request withdrawn
+    (cancel_at reached) while it waits leaves the queue without taking a slot or any
+    budget; one withdrawn while it runs has its output dropped, and its slot and
+    bytes return when the device finishes the work already enqueued on it (a stream
+    cannot take back enqueued work).  Cancelled requests get no `done` time.
+    `trace`, if given, receives (time, bytes in use, active count) after every change.
     """
     pending = collections.deque(sorted(reqs, key=lambda q: q.arrival))
     active = {}
@@ -173,10 +179,25 @@ def run_batched(reqs, wl, executor, budget_bytes: float = 200e9, clock=time.perf
     while pending or active:
         now = clock() - t0
         changed = False
+        if any(r.cancel_at is not None and r.cancel_at <= now for r in pending):
+            keep = collections.deque()
+            for r in pending:
+                if r.cancel_at is not None and r.cancel_at <= now:
+                    r.cancelled = True
+                    changed = True
+                else:
+                    keep.append(r)
+            pending = keep
         for slot in list(active):
+            r = active[slot][0]
+            if not r.cancelled and r.cancel_at is not None and r.cancel_at <= now:
+                r.cancelled = True
+                r.output = None
+                changed = True
             if executor.poll(slot):
                 r, plan = active.pop(slot)
-                r.done = clock() - t0
+                if not r.cancelled:
+                    r.done = clock() - t0
                 in_use -= r.bytes
                 plan.close()
                 changed = True

@@ -77,6 +77,25 @@ def test_plain_and_batched_agree_and_match_oracle(small):
     ex.close()
 
 
+def test_withdrawn_requests_leave_the_others_unchanged(small):
+    """Two requests withdrawn while they wait never start; every other request still
+    completes, bitwise equal to the same request run alone."""
+    wl, reqs = small
+    ex = el.Executor(max_slots=2, chunk=16)
+    reqs = SV.clone_requests(reqs)
+    for k in (3, 6):
+        reqs[k].cancel_at = 0.0
+    out = SV.run_batched(reqs, wl, ex, budget_bytes=1e12)
+    for r in out:
+        if r.rid in (3, 6):
+            assert r.cancelled and r.admitted is None and r.done is None
+        else:
+            assert not r.cancelled and r.done is not None
+            assert torch.equal(r.output, _alone(wl, r)), (r.rid, r.op, r.n, r.nsteps)
+    assert ex.slots()[1] == 0
+    ex.close()
+
+
 def test_budget_limits_concurrency(small):
     wl, reqs = small
     ex = el.Executor(max_slots=3, chunk=16)

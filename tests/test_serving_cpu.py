@@ -119,3 +119,56 @@ def test_request_mix_statistics():
     assert {r.n for r in reqs} == set(SV.SIZES)
     assert all(256 <= r.nrec <= 1024 for r in reqs)
     assert all(r.nsteps == 800 + (r.n - 96) * 1000 // 160 for r in reqs)
+
+
+class TaggedWorkloads(MockWorkloads):
+    """Plans that carry their request, so a mock start can look up its duration."""
+
+    def plan(self, r):
+        p = MockPlan()
+        p.req = r
+        return p
+
+
+def _run_tagged(reqs, budget, slots=1):
+    clk = Clock()
+    ex = MockExecutor(clk, max_slots=slots)
+    orig_start = ex.start
+    started = []
+
+    def start(plan, op, inp, out):
+        ex._dur = plan.req.cell_updates / ex.rate
+        started.append(plan.req.rid)
+        return orig_start(plan, op, inp, out)
+
+    ex.start = start
+    trace = []
+    SV.run_batched(reqs, TaggedWorkloads(), ex, budget_bytes=budget, clock=clk, sleep=clk.sleep, trace=trace)
+    return reqs, started, trace
+
+
+def test_cancelled_waiting_request_takes_no_slot():
+    """With one slot, request 1 waits behind request 0 and is withdrawn while waiting: it is
+    never started, takes no budget, and request 2 follows request 0 directly."""
+    reqs = [SV.Request(rid=k, op=0, n=32, nsteps=200, nrec=8, seed=k, arrival=0.001 * k) for k in range(3)]
+    dur = reqs[0].cell_updates / 5e9
+    reqs[1].cancel_at = 0.5 * dur
+    out, started, trace = _run_tagged(reqs, budget=1e12, slots=1)
+    assert started == [0, 2]
+    assert out[1].cancelled and out[1].admitted is None and out[1].done is None
+    assert out[0].done is not None and out[2].done is not None
+    assert out[2].admitted >= out[0].done
+    assert SV.summarize(out)["n"] == 2
+
+
+def test_cancelled_running_request_frees_its_slot_when_the_device_finishes():
+    """Request 0 is withdrawn while it runs: its output is dropped, it gets no done time,
+    and its slot and bytes return when its enqueued work ends, admitting request 1."""
+    reqs = [SV.Request(rid=k, op=0, n=32, nsteps=200, nrec=8, seed=k, arrival=0.001 * k) for k in range(2)]
+    dur = reqs[0].cell_updates / 5e9
+    reqs[0].cancel_at = 0.3 * dur
+    out, started, trace = _run_tagged(reqs, budget=1e12, slots=1)
+    assert started == [0, 1]
+    assert out[0].cancelled and out[0].output is None and out[0].done is None
+    assert out[1].admitted >= dur and out[1].done is not None
+    assert trace[-1][1] == 0 and trace[-1][2] == 0     # nothing held at the end

@@ -244,11 +244,12 @@ typedef struct el_fluid_stats {
 el_status el_plan_fluid_path(el_plan plan, int32_t enable, el_fluid_stats *stats);
 
 /* Kernel kinds reported by el_plan_kernel_time(). */
-#define EL_K_VELOCITY     0   /* forward velocity pass (+ phi slabs)           */
+#define EL_K_VELOCITY     0   /* forward velocity pass (+ phi slabs; it also   */
+                              /* gathers the previous trace row)               */
 #define EL_K_STRESS       1   /* forward stress pass (+ psi slabs)             */
 #define EL_K_ADJ_VELOCITY 2   /* adjoint pass producing the velocity adjoint   */
 #define EL_K_ADJ_STRESS   3   /* adjoint pass producing the stress adjoint     */
-#define EL_K_GATHER       4   /* receiver gather (forward)                     */
+#define EL_K_GATHER       4   /* receiver gather of the last trace row         */
 #define EL_K_SCATTER      5   /* receiver scatter (adjoint)                    */
 #define EL_K_COUNT        6
 

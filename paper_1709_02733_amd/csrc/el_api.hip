@@ -453,13 +453,16 @@ el_status run_forward(el_plan p, Dev<T> &d, const T *p0, double *traces, hipStre
     const int M = p->g.nsteps, L = p->nrec;
     HIP_TRY(launch_zero_state(d, s), "zero state");
     HIP_TRY(launch_inject(d, p0, s), "inject");
-    HIP_TRY(timed(p, EL_K_GATHER, 0, s, [&] { return launch_gather(d, p->rec, traces, s); }), "gather");
+    // trace row m-1 is gathered by extra blocks of velocity pass m (which reads those stresses
+    // and writes none); the last row by a gather launch of its own
     for (int m = 1; m < M; ++m) {
-        HIP_TRY(timed(p, EL_K_VELOCITY, m, s, [&] { return launch_velocity(d, p->tiles, s); }), "velocity pass");
+        double *row = traces + (size_t)(m - 1) * L;
+        HIP_TRY(timed(p, EL_K_VELOCITY, m, s, [&] { return launch_velocity(d, p->tiles, s, &p->rec, row); }),
+                "velocity pass");
         HIP_TRY(timed(p, EL_K_STRESS, m, s, [&] { return launch_stress(d, p->tiles, s); }), "stress pass");
-        HIP_TRY(timed(p, EL_K_GATHER, m, s, [&] { return launch_gather(d, p->rec, traces + (size_t)m * L, s); }),
-                "gather");
     }
+    HIP_TRY(timed(p, EL_K_GATHER, M - 1, s, [&] { return launch_gather(d, p->rec, traces + (size_t)(M - 1) * L, s); }),
+            "gather");
     if (p->fluid_path && p->fast_tiles > 0) HIP_TRY(launch_fluid_fill(d, p->tiles, s), "fluid fill");
     return EL_OK;
 }

@@ -158,6 +158,32 @@ struct Rec {
     const double *ent_w;     // weight of each entry
 };
 
+// Receiver gather: p_hat_m[l] = -sum_c w_lc (s11 + s22 + s33)[c]  (Sec. 3, eq. interpgrid), in
+// double.  One wavefront serves 8 receivers; lane = 8 * receiver + corner, reduced over 8
+// lanes.  On a fluid tile s22 = s33 = s11 (the lean stress loop stores s11 alone there), and
+// the trace is taken as 3 s11, the same double as the sum of the three equal terms.
+template <typename T>
+__device__ __forceinline__ double trace_at(const Dev<T> &d, const Rec &r, int e) {
+    const long long q = r.idx[e];
+    const double s11 = (double)d.f[S11][q];
+    return r.fl[e] ? 3.0 * s11 : s11 + (double)d.f[S22][q] + (double)d.f[S33][q];
+}
+// The receivers of gather block gb (256 threads: 4 wavefronts, 32 receivers) into out[].
+template <typename T>
+__device__ __forceinline__ void gather_block(const Dev<T> &d, const Rec &r, double *out, int gb) {
+    const int lane = threadIdx.x & 63;
+    const int wave = (gb * 256 + (int)threadIdx.x) >> 6;
+    const int l = wave * 8 + (lane >> 3);
+    const int c = lane & 7;
+    double v = 0.0;
+    if (l < r.nrec) v = r.w[8 * l + c] * trace_at(d, r, 8 * l + c);
+    v += __shfl_xor(v, 1);
+    v += __shfl_xor(v, 2);
+    v += __shfl_xor(v, 4);
+    if (l < r.nrec && c == 0) out[l] = -v;
+}
+inline int gather_blocks(int nrec) { return ((nrec + 7) / 8 + 3) / 4; }
+
 // Workspace layout (byte offsets), computed identically for sizing and binding.
 struct Layout {
     size_t field[NFIELD];
@@ -189,7 +215,10 @@ template <typename T> hipError_t launch_classify(const Dev<T> &d, const Tiles &t
                                                  unsigned char *uni, T *med, unsigned long long *lanes,
                                                  hipStream_t s);
 template <typename T> hipError_t launch_inject(const Dev<T> &d, const T *p0, hipStream_t s);
-template <typename T> hipError_t launch_velocity(const Dev<T> &d, const Tiles &tl, hipStream_t s);
+// The forward velocity launch can also gather a trace row (grow != null) from the stresses it
+// reads and does not write: extra blocks after the tiles' run gather_block.
+template <typename T> hipError_t launch_velocity(const Dev<T> &d, const Tiles &tl, hipStream_t s,
+                                                 const Rec *r = nullptr, double *grow = nullptr);
 template <typename T> hipError_t launch_stress(const Dev<T> &d, const Tiles &tl, hipStream_t s);
 template <typename T> hipError_t launch_gather(const Dev<T> &d, const Rec &r, double *trace_row, hipStream_t s);
 template <typename T> hipError_t launch_adj_velocity(const Dev<T> &d, const Tiles &tl, hipStream_t s);

@@ -307,37 +307,16 @@ hipError_t launch_inject(const Dev<T> &d, const T *p0, hipStream_t s) {
 
 // ------------------------------------------------------- receivers
 
-// p_hat_m[l] = -sum_c w_lc (s11 + s22 + s33)[c]  (Sec. 3, eq. interpgrid), in double.
-// One wavefront serves 8 receivers; lane = 8 * receiver + corner, reduced over 8 lanes.
-// On a fluid tile s22 = s33 = s11 (the lean stress loop stores s11 alone there), and the
-// trace is taken as 3 s11, the same double as the sum of the three equal terms.
+// Receiver gather (gather_block in el_impl.h), standalone.
 template <typename T>
-__device__ __forceinline__ double trace_at(const Dev<T> &d, const Rec &r, int e) {
-    const long long q = r.idx[e];
-    const double s11 = (double)d.f[S11][q];
-    return r.fl[e] ? 3.0 * s11 : s11 + (double)d.f[S22][q] + (double)d.f[S33][q];
-}
-
-template <typename T>
-__global__ void k_gather(Dev<T> d, Rec r, double *out) {
-    const int lane = threadIdx.x & 63;
-    const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    const int l = wave * 8 + (lane >> 3);
-    const int c = lane & 7;
-    double v = 0.0;
-    if (l < r.nrec) v = r.w[8 * l + c] * trace_at(d, r, 8 * l + c);
-    v += __shfl_xor(v, 1);
-    v += __shfl_xor(v, 2);
-    v += __shfl_xor(v, 4);
-    if (l < r.nrec && c == 0) out[l] = -v;
+__global__ __launch_bounds__(256) void k_gather(Dev<T> d, Rec r, double *out) {
+    gather_block(d, r, out, (int)blockIdx.x);
 }
 
 template <typename T>
 hipError_t launch_gather(const Dev<T> &d, const Rec &r, double *row, hipStream_t s) {
     if (r.nrec == 0) return hipSuccess;
-    const int waves = (r.nrec + 7) / 8;
-    const int blocks = (waves + 3) / 4;
-    hipLaunchKernelGGL(k_gather<T>, dim3(blocks), dim3(256), 0, s, d, r, row);
+    hipLaunchKernelGGL(k_gather<T>, dim3(gather_blocks(r.nrec)), dim3(256), 0, s, d, r, row);
     return hipGetLastError();
 }
 

@@ -314,7 +314,14 @@ __device__ __forceinline__ void fluid_vel(const Dev<T> &d, int i, int j, int z0,
 }
 
 template <typename T, bool ADJ>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 5 : 1))) void k_vel(Dev<T> d, Tiles tl) {
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 5 : 1))) void k_vel(Dev<T> d, Tiles tl,
+                                                                                                   Rec r, double *grow) {
+    static_assert(NT == 256, "gather_block works on blocks of 256 threads");
+    if (!ADJ && grow && (int)blockIdx.x >= 8 * tl.per) {
+        // the trace row of the stresses this pass reads (the previous step's), see launch_velocity
+        gather_block(d, r, grow, (int)blockIdx.x - 8 * tl.per);
+        return;
+    }
     int x0, y0, z0, z1, t = 0, edges = 0;
     bool fast = false, uni = false, cols = false;
     if (!tile_of(tl, d.nz, x0, y0, z0, z1, t, fast, uni, cols, edges)) return;
@@ -783,8 +790,10 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
 }
 
 template <typename T>
-hipError_t launch_velocity(const Dev<T> &d, const Tiles &tl, hipStream_t s) {
-    hipLaunchKernelGGL((k_vel<T, false>), dim3(8 * tl.per), dim3(NT), 0, s, d, tl);
+hipError_t launch_velocity(const Dev<T> &d, const Tiles &tl, hipStream_t s, const Rec *r, double *grow) {
+    const bool g = r && grow && r->nrec > 0;
+    const int blocks = 8 * tl.per + (g ? gather_blocks(r->nrec) : 0);
+    hipLaunchKernelGGL((k_vel<T, false>), dim3(blocks), dim3(NT), 0, s, d, tl, g ? *r : Rec{}, g ? grow : nullptr);
     return hipGetLastError();
 }
 template <typename T>
@@ -794,7 +803,7 @@ hipError_t launch_stress(const Dev<T> &d, const Tiles &tl, hipStream_t s) {
 }
 template <typename T>
 hipError_t launch_adj_velocity(const Dev<T> &d, const Tiles &tl, hipStream_t s) {
-    hipLaunchKernelGGL((k_vel<T, true>), dim3(8 * tl.per), dim3(NT), 0, s, d, tl);
+    hipLaunchKernelGGL((k_vel<T, true>), dim3(8 * tl.per), dim3(NT), 0, s, d, tl, Rec{}, (double *)nullptr);
     return hipGetLastError();
 }
 template <typename T>
@@ -827,7 +836,7 @@ hipError_t launch_fluid_fill(const Dev<T> &d, const Tiles &tl, hipStream_t s) {
 
 #define EL_STENCIL_INST(T)                                                                  \
     template hipError_t launch_fluid_fill<T>(const Dev<T> &, const Tiles &, hipStream_t);   \
-    template hipError_t launch_velocity<T>(const Dev<T> &, const Tiles &, hipStream_t);     \
+    template hipError_t launch_velocity<T>(const Dev<T> &, const Tiles &, hipStream_t, const Rec *, double *); \
     template hipError_t launch_stress<T>(const Dev<T> &, const Tiles &, hipStream_t);       \
     template hipError_t launch_adj_velocity<T>(const Dev<T> &, const Tiles &, hipStream_t); \
     template hipError_t launch_adj_stress<T>(const Dev<T> &, const Tiles &, hipStream_t);

@@ -379,6 +379,21 @@ def test_full_size_state_and_traces(skull384):
     assert rel_max(tr, tr_ref) <= 1e-5
 
 
+def test_full_size_full_length_dot_product():
+    """The benchmark's workload itself (384^3 skull medium, M = 2500, L = 1024, C-PML, fluid
+    path as launched by bench.py): <H p, y> = <p, H^T y> for random p and y = H q, within
+    the FP32 bound of the dot test."""
+    sc = S.make("skull384")
+    plan = el.Plan.from_scenario(sc)
+    st = plan.fluid_stats()
+    assert st["cells"] > 0.9 * sc.ncells and st["uniform_cells"] > 0.9 * sc.ncells
+    r = _dot_residual(plan, sc, 11)
+    banner(f"384^3, M={sc.nsteps}: dot residual {r:.3e}")
+    del plan
+    torch.cuda.empty_cache()
+    assert r <= 1e-5
+
+
 def test_full_size_adjoint(skull384):
     sc = skull384
     plan = el.Plan.from_scenario(sc)

@@ -214,10 +214,12 @@ el_status el_plan_sizes(el_plan plan, int64_t *ncells, int32_t *nrec, int32_t *n
  * coupling medium such as the water of Sec. 7) takes the three values from
  * a per-tile table instead of the maps, again with the same results.
  * Inside the other tiles, every column of 1 x 1 cells by the chunk whose
- * cells within two have mu = 0 is marked too, and its lanes run the same
- * fluid update (storing all three normal stresses); a column whose box holds
- * the tile's reference medium (that of its first fluid column) takes it from
- * the table as well.
+ * cells within two have mu = 0 is marked too and takes the fluid update,
+ * storing all three normal stresses: a row of such columns runs the fluid
+ * loop, and in a row that also holds other columns the fluid lanes run the
+ * general loop without the loads they do not need (shear stresses, moduli).
+ * A column whose box holds the tile's reference medium (that of its first
+ * fluid column) takes it from the table as well.
  */
 typedef struct el_fluid_stats {
     int64_t tiles;           /* tiles that take the fluid update                   */

@@ -284,6 +284,24 @@ def test_fluid_tiles_dot_product():
     assert r <= 1e-5
 
 
+def test_zero_receivers():
+    """L = 0: the forward returns an (M, 0) trace array and leaves the wavefield state
+    bitwise as with receivers; the adjoint of no data is zero."""
+    sc = S.random_scenario((70, 18, 16), seed=3, nsteps=12, npml=2, nrec=4, fluid_fraction=0.8)
+    p = torch.from_numpy(sc.p0)
+    with_rec = el.Plan.from_scenario(sc)
+    with_rec.forward(p)
+    ref = {f: with_rec.field(f).cpu().clone() for f in el.FIELDS}
+    sc.rec = np.zeros((0, 3))
+    plan = el.Plan.from_scenario(sc)
+    tr = plan.forward(p)
+    assert tuple(tr.shape) == (sc.nsteps, 0)
+    for f in el.FIELDS:
+        assert torch.equal(plan.field(f).cpu(), ref[f]), f
+    pa = plan.adjoint(torch.zeros((sc.nsteps, 0), dtype=torch.float64))
+    assert pa.abs().max().item() == 0.0
+
+
 def test_receivers_on_faces_and_corners():
     sc = S.random_scenario((14, 12, 10), seed=11, nsteps=15, npml=2, nrec=1)
     rec = np.array([[0, 0, 0], [13, 11, 9], [13, 0, 4.5], [6.5, 11, 0], [0.25, 5.75, 9]]) * sc.dx

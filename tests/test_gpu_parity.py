@@ -48,6 +48,8 @@ CASES = [
     ((17, 29, 8), 0, 30, 3, 0.6),      # no PML
     ((10, 10, 10), 4, 20, 4, 0.0),     # minimum size for npml = 4 (2P + 2), all solid
     ((12, 11, 13), 2, 1, 5, 0.5),      # one sample: no update at all
+    ((4, 4, 4), 0, 15, 6, 1.0),        # smallest grid, all fluid: one fluid tile
+    ((10, 10, 10), 4, 20, 7, 1.0),     # all fluid with npml = 4: the fluid loops write both slab copies
 ]
 
 

@@ -15,6 +15,7 @@ import pytest
 
 from oracle.oracle import Model
 from oracle.assembly import Assembly
+from oracle.energy import energy_series, modified_energy
 from paper_1709_02733_amd import scenarios as S
 from tests.polyfield import Poly, staggered_coords, U_OFF, SIG_OFF, VOIGT
 
@@ -263,54 +264,56 @@ def test_dot_product_fp64(shape, npml, nsteps, seed):
 # absorption and PML off
 # --------------------------------------------------------------------------
 
-def _energy(m, cf, u_prev, u_next, sig):
-    rho_u = cf["rho_u"]
-    kin = 0.5 * sum(np.sum(rho_u[i] * u_prev[i] * u_next[i]) for i in range(3))
-    lam, mu = cf["lam"], cf["mu"]
-    K = lam + 2.0 * mu / 3.0
+def _state_checks(cf, sig):
+    """Fluid points keep a zero deviatoric stress and zero-modulus edges a zero shear
+    stress (Sec. 2.1), so dropping those terms from the energy loses nothing."""
     tr = sig[0] + sig[1] + sig[2]
-    pot = np.sum(tr * tr / (9.0 * K))
-    solid = mu > 0
     dev2 = sum((sig[i] - tr / 3.0) ** 2 for i in range(3))
-    assert np.all(dev2[~solid] <= 1e-24 * (1.0 + np.max(tr * tr)))
-    pot += np.sum(dev2[solid] / (2.0 * mu[solid]))
+    assert np.all(dev2[cf["mu"] == 0] <= 1e-24 * (1.0 + np.max(tr * tr)))
     for a, sid in ((3, 0), (4, 1), (5, 2)):
-        ms = cf["mu_s"][sid]
-        nz = ms > 0
-        assert np.all(sig[a][~nz] == 0.0)
-        pot += np.sum(sig[a][nz] ** 2 / ms[nz])
-    return kin + 0.5 * pot
+        assert np.all(sig[a][cf["mu_s"][sid] == 0] == 0.0)
+
+
+def _energies(m, p0, steps):
+    cf = m.coefficients()
+    v = m.inject(p0)
+    sv = m.state_views(v)
+    E = []
+    for _ in range(steps):
+        u_prev = [a.copy() for a in sv["u"]]
+        sig = [a.copy() for a in sv["sig"]]
+        _state_checks(cf, sig)
+        m.step(v)
+        E.append(modified_energy(cf, u_prev, sv["u"], sig))
+    return np.array(E)
 
 
 def test_energy_conserved_without_absorption_and_pml():
     sc = S.random_scenario((18, 16, 14), seed=4, nsteps=2, npml=0, nrec=1, absorption=False)
     m = _model(sc)
-    cf = m.coefficients()
-    v = m.inject(sc.p0)
-    E = []
-    sv = m.state_views(v)
-    for _ in range(400):
-        u_prev = [a.copy() for a in sv["u"]]
-        sig = [a.copy() for a in sv["sig"]]
-        m.step(v)
-        E.append(_energy(m, cf, u_prev, sv["u"], sig))
-    E = np.array(E)
+    E = _energies(m, sc.p0, 400)
     assert E[0] > 0
     assert np.max(np.abs(E - E[0])) <= 1e-12 * E[0]
+    # the series helper samples the same recursion
+    Es = energy_series(m, sc.p0, 401, every=40)
+    assert np.array_equal(Es, E[::40])
+
+
+def test_initial_energy_closed_form():
+    # u_{-1/2} = 0 and sigma_0 = -p0/3 I: only the trace term remains, with tr sigma_0 = -p0,
+    # so E_0 = sum p0^2 / (18 K), K = lambda + 2 mu / 3 (a solid and fluid medium)
+    sc = S.random_scenario((11, 10, 9), seed=8, nsteps=2, npml=2, nrec=1)
+    assert np.any(sc.mu > 0) and np.any(sc.mu == 0)
+    m = _model(sc)
+    K = sc.lam.astype(np.float64) + 2.0 * sc.mu.astype(np.float64) / 3.0
+    ref = np.sum(sc.p0.astype(np.float64) ** 2 / (18.0 * K))
+    E0 = energy_series(m, sc.p0, 2)[0]
+    assert abs(E0 - ref) <= 1e-13 * ref
 
 
 def test_energy_decays_with_absorption():
     sc = S.random_scenario((14, 14, 14), seed=4, nsteps=2, npml=0, nrec=1, absorption=True)
-    m = _model(sc)
-    cf = m.coefficients()
-    v = m.inject(sc.p0)
-    sv = m.state_views(v)
-    E = []
-    for _ in range(150):
-        u_prev = [a.copy() for a in sv["u"]]
-        sig = [a.copy() for a in sv["sig"]]
-        m.step(v)
-        E.append(_energy(m, cf, u_prev, sv["u"], sig))
+    E = _energies(_model(sc), sc.p0, 150)
     assert E[-1] < E[0]
     assert np.all(np.diff(E) <= 1e-12 * E[0])
 

@@ -90,7 +90,9 @@ const char *el_last_error(void);
 
 /*
  * Host-only checks of a grid and a receiver set: sizes, spacing, PML
- * thickness, precision, and that every receiver lies in [0, n-1]*dx (up to
+ * thickness, precision, that every array the kernels address (a padded
+ * volume, a C-PML memory-variable slab of 2 (npml + 7) planes) stays below
+ * 4 GiB, and that every receiver lies in [0, n-1]*dx (up to
  * 1e-9 cells of rounding; such receivers are clamped onto the box).
  * rec_xyz (host): nrec x 3 doubles, metres from the centre of cell (0,0,0),
  * columns x, y, z.  nrec may be 0 (rec_xyz may then be NULL).
@@ -111,7 +113,8 @@ el_status el_plan_bytes(const el_grid *grid, int32_t nrec, size_t *bytes);
  * trilinear receiver tables (Sec. 3, eq. interpgrid).
  *   lambda, mu, rho, alpha (device): N = nx*ny*nz floats each, cell values
  *       in Pa, Pa, kg/m^3, 1/s.  Checked on the device: rho > 0, mu >= 0,
- *       lambda + 2 mu > 0, 0 <= dt*alpha < 1, all finite (EL_EINVAL /
+ *       lambda + 2 mu > 0, 3 lambda + 2 mu > 0 (a positive bulk modulus,
+ *       Sec. 2.1), 0 <= dt*alpha < 1, all finite (EL_EINVAL /
  *       EL_EUNSTABLE), and max sqrt((lambda+2mu)/rho) dt/dx <= 6/(7 sqrt 3)
  *       (EL_EUNSTABLE).  They may be freed once this call returns.
  *   rec_xyz (host): nrec x 3 doubles as in el_grid_check().
@@ -135,6 +138,31 @@ el_status el_plan_destroy(el_plan plan);
  * Asynchronous on `stream`.
  */
 el_status el_forward(el_plan plan, const void *p0, double *traces, void *stream);
+
+/*
+ * traces = H p0 as el_forward (the same kernels, bit for bit the same traces
+ * and final state), and the modified energy of the leapfrog recursion
+ * (Sec. 2.2, eq. it) at every `every`-th time level m = 0, every, 2 every,
+ * ... <= nsteps - 2, accumulated in double on the device:
+ *
+ *   E_m = 1/2 sum_c sum_cells rho_c u^c_{m-1/2} u^c_{m+1/2} + 1/2 sigma_m^T C^+ sigma_m
+ *
+ * with u_{-1/2} = 0, rho_c the staggered density of the update, and
+ * sigma^T C^+ sigma = (tr s)^2 / (9K) + |dev s|^2 / (2 mu) at normal points
+ * (K = lambda + 2 mu / 3; the second term only where mu > 0) plus
+ * s_ij^2 / mu_ij at shear points (only where the harmonic-mean edge modulus
+ * mu_ij is nonzero).  The scheme is skew with a symmetric stiffness, so with
+ * alpha = 0 and npml = 0 E_m stays constant up to rounding; absorption and
+ * the C-PML make it decay.  The C-PML memory variables are not part of E_m.
+ *   every: >= 1.
+ *   energy (device): ceil((nsteps - 1) / every) doubles (none when
+ *       nsteps = 1; energy may then be NULL), fully overwritten in order of m.
+ * Deterministic (fixed reduction order).  Asynchronous on `stream`.
+ * Errors: EL_EINVAL for a NULL plan, p0, traces (nrec > 0) or energy, or
+ * every < 1.
+ */
+el_status el_forward_energy(el_plan plan, const void *p0, double *traces, int32_t every, double *energy,
+                            void *stream);
 
 /*
  * p_adj = H^T y, by the backward recursion v_{m-1} = Theta^T y_{m-1} + W'^T v_m
@@ -295,8 +323,14 @@ el_status el_exec_create(el_exec *out, int32_t max_slots, int32_t chunk_steps);
 /* Wait for every slot, then release the executor. */
 el_status el_exec_destroy(el_exec ex);
 
-/* Start `op` on a free slot; *slot receives its index.  EL_EBUSY if all slots are busy. */
-el_status el_exec_start(el_exec ex, el_plan plan, int32_t op, const void *in, void *out, int32_t *slot);
+/*
+ * Start `op` on a free slot; *slot receives its index.  EL_EBUSY if all slots
+ * are busy.  The operation runs after all work enqueued so far on `stream`
+ * (the caller's stream that writes `in` or last used `out`; NULL = the null
+ * stream) and after the plan's previous operation.
+ */
+el_status el_exec_start(el_exec ex, el_plan plan, int32_t op, const void *in, void *out, void *stream,
+                        int32_t *slot);
 
 /* Non-blocking: *done = 1 once the slot's operation has completed (the slot is then free). */
 el_status el_exec_poll(el_exec ex, int32_t slot, int32_t *done);

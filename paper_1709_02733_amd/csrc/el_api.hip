@@ -102,8 +102,9 @@ bool layout(const el_grid &g, int nrec, Layout *L) {
         L->tile_flags = take(2 * (size_t)t.ntiles);
         L->tile_media = take((size_t)4 * t.ntiles * es);
         L->tile_lanes = take((size_t)2 * kTileY * t.ntiles * 8);
+        L->energy = take((size_t)(kTileX * kTileY + 2) * 8 * t.per * sizeof(double));
     }
-    L->partial = take(7 * kDotBlocks * 8);
+    L->partial = take(kStats * kDotBlocks * 8);
     L->total = off;
     return true;
 }
@@ -211,6 +212,18 @@ el_status el_grid_check(const el_grid *g, const double *rec, int32_t nrec) {
         if (bytes >= (1LL << 32))
             return fail(EL_EINVAL, "grid %dx%dx%d: one padded volume array needs %lld bytes; the kernels address at most 4 GiB per array",
                         g->nx, g->ny, g->nz, bytes);
+        // the C-PML memory variables of axis a live on W = 2 (P + 7) planes of that axis
+        // (slab_byte forms 32-bit byte offsets into them as well)
+        if (g->npml > 0) {
+            const long long W = 2LL * (g->npml + 7);
+            const long long slab[3] = {W * g->ny * g->nz, W * g->nx * g->nz, W * g->nx * g->ny};
+            for (int a = 0; a < 3; ++a)
+                if (slab[a] * es >= (1LL << 32))
+                    return fail(EL_EINVAL,
+                                "grid %dx%dx%d, npml %d: a C-PML memory-variable array of axis %d needs %lld bytes; "
+                                "the kernels address at most 4 GiB per array",
+                                g->nx, g->ny, g->nz, g->npml, a, slab[a] * es);
+        }
         const long long tiles = (long long)((g->nx + kTileX - 1) / kTileX) * ((g->ny + kTileY - 1) / kTileY) *
                                 ((g->nz + kZChunk - 1) / kZChunk);
         if (tiles > kTileMask)
@@ -448,17 +461,29 @@ hipError_t timed(el_plan p, int kind, int m, hipStream_t s, F launch) {
     return hipEventRecord(pr.second, s);
 }
 
+// energy != null: also the modified energy E_{m-1} = (kinetic + potential) / 2 of every
+// `every`-th level m - 1, formed during update m (the velocity pass, which turns u_{m-3/2}
+// into u_{m-1/2} while sigma_{m-1} stays in place) into energy[(m - 1) / every].
 template <typename T>
-el_status run_forward(el_plan p, Dev<T> &d, const T *p0, double *traces, hipStream_t s) {
+el_status run_forward(el_plan p, Dev<T> &d, const T *p0, double *traces, hipStream_t s, int every = 0,
+                      double *energy = nullptr) {
     const int M = p->g.nsteps, L = p->nrec;
+    const int nb = 8 * p->tiles.per;
+    double *ekin = reinterpret_cast<double *>(p->ws + p->L.energy);   // per thread
+    double *ekb = ekin + (size_t)nb * kTileX * kTileY;                 // per block
+    double *epot = ekb + nb;
     HIP_TRY(launch_zero_state(d, s), "zero state");
     HIP_TRY(launch_inject(d, p0, s), "inject");
     // trace row m-1 is gathered by extra blocks of velocity pass m (which reads those stresses
     // and writes none); the last row by a gather launch of its own
     for (int m = 1; m < M; ++m) {
         double *row = traces + (size_t)(m - 1) * L;
-        HIP_TRY(timed(p, EL_K_VELOCITY, m, s, [&] { return launch_velocity(d, p->tiles, s, &p->rec, row); }),
+        const bool en = energy && (m - 1) % every == 0;
+        if (en) HIP_TRY(launch_energy_pot(d, p->tiles, epot, s), "potential energy");
+        HIP_TRY(timed(p, EL_K_VELOCITY, m, s,
+                      [&] { return launch_velocity(d, p->tiles, s, &p->rec, row, en ? ekin : nullptr); }),
                 "velocity pass");
+        if (en) HIP_TRY(launch_energy_final(ekin, ekb, epot, nb, energy + (m - 1) / every, s), "energy");
         HIP_TRY(timed(p, EL_K_STRESS, m, s, [&] { return launch_stress(d, p->tiles, s); }), "stress pass");
     }
     HIP_TRY(timed(p, EL_K_GATHER, M - 1, s, [&] { return launch_gather(d, p->rec, traces + (size_t)(M - 1) * L, s); }),
@@ -526,7 +551,7 @@ el_status el_plan_create(el_plan *out, const el_grid *grid, const float *lam, co
     double *partial = reinterpret_cast<double *>(p->ws + L.partial);
     hipError_t e = launch_media_stats(lam, mu, rho, alpha, p->N, grid->dt, stats, partial, s);
     if (e != hipSuccess) return bail(hip_fail(e, "media statistics"));
-    double hs[7];
+    double hs[kStats];
     e = hipMemcpyAsync(hs, stats, sizeof hs, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return bail(hip_fail(e, "media statistics"));
@@ -534,6 +559,8 @@ el_status el_plan_create(el_plan *out, const el_grid *grid, const float *lam, co
     if (!(hs[1] > 0)) return bail(fail(EL_EINVAL, "rho must be > 0 (min %.6g)", hs[1]));
     if (hs[2] < 0) return bail(fail(EL_EINVAL, "mu must be >= 0 (min %.6g)", hs[2]));
     if (!(hs[3] > 0)) return bail(fail(EL_EINVAL, "lambda + 2 mu must be > 0 (min %.6g)", hs[3]));
+    // a positive bulk modulus (Sec. 2.1): the adjoint state w = C s divides by 3 lambda + 2 mu
+    if (!(hs[7] > 0)) return bail(fail(EL_EINVAL, "3 lambda + 2 mu must be > 0 (min %.6g)", hs[7]));
     if (hs[5] < 0 || hs[4] >= 1.0)
         return bail(fail(EL_EUNSTABLE, "dt*alpha must lie in [0, 1) (range %.6g .. %.6g)", hs[5], hs[4]));
     p->cmax = std::sqrt(hs[0]);
@@ -680,6 +707,22 @@ el_status el_forward(el_plan p, const void *p0, double *traces, void *stream) {
     HIP_TRY(hipStreamWaitEvent(s, p->done, 0), "order after the previous operation");
     st = p->g.precision == EL_F64 ? run_forward(p, p->dd, static_cast<const double *>(p0), traces, s)
                                   : run_forward(p, p->df, static_cast<const float *>(p0), traces, s);
+    if (st != EL_OK) return st;
+    HIP_TRY(hipEventRecord(p->done, s), "record completion");
+    return EL_OK;
+}
+
+el_status el_forward_energy(el_plan p, const void *p0, double *traces, int32_t every, double *energy, void *stream) {
+    el_status st = check_plan(p);
+    if (st != EL_OK) return st;
+    if (!p0 || (!traces && p->nrec > 0)) return fail(EL_EINVAL, "p0 or traces is NULL");
+    if (every < 1) return fail(EL_EINVAL, "every must be >= 1");
+    if (!energy && p->g.nsteps > 1) return fail(EL_EINVAL, "energy is NULL");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    HIP_TRY(hipStreamWaitEvent(s, p->done, 0), "order after the previous operation");
+    st = p->g.precision == EL_F64
+             ? run_forward(p, p->dd, static_cast<const double *>(p0), traces, s, every, energy)
+             : run_forward(p, p->df, static_cast<const float *>(p0), traces, s, every, energy);
     if (st != EL_OK) return st;
     HIP_TRY(hipEventRecord(p->done, s), "record completion");
     return EL_OK;

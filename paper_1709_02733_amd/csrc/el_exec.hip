@@ -19,6 +19,7 @@ struct ExecSlot {
     bool busy = false;
     hipStream_t stream = nullptr;
     hipEvent_t done = nullptr;
+    hipEvent_t ready = nullptr;   // inputs written: recorded on the caller's stream
     el_plan plan = nullptr;
     hipGraphExec_t graph[2] = {nullptr, nullptr};
 };
@@ -79,11 +80,15 @@ el_status capture(el_plan p, const Dev<T> &d, int op, int steps, void *traces, i
 }
 
 template <typename T>
-el_status start_op(el_exec ex, ExecSlot &sl, el_plan p, const Dev<T> &d, int op, const void *in, void *out) {
+el_status start_op(el_exec ex, ExecSlot &sl, el_plan p, const Dev<T> &d, int op, const void *in, void *out,
+                   hipStream_t after) {
     const hipStream_t s = sl.stream;
     const int M = p->g.nsteps, L = p->nrec;
     int *ctr = reinterpret_cast<int *>(p->ws + p->L.counter);
     void *traces = op == EL_OP_FORWARD ? out : const_cast<void *>(in);
+    // the caller's stream may still be writing the input (or using the output)
+    EX_TRY(hipEventRecord(sl.ready, after), "record the caller's stream");
+    EX_TRY(hipStreamWaitEvent(s, sl.ready, 0), "order after the caller's stream");
     EX_TRY(hipStreamWaitEvent(s, p->done, 0), "order after the plan's previous operation");
     EX_TRY(launch_zero_state(d, s), "zero state");
     if (op == EL_OP_FORWARD) {
@@ -151,6 +156,7 @@ el_status el_exec_create(el_exec *out, int32_t max_slots, int32_t chunk_steps) {
     for (auto &sl : ex->slots) {
         if (e == hipSuccess) e = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&sl.ready, hipEventDisableTiming);
     }
     if (e != hipSuccess) {
         el_exec_destroy(ex);
@@ -166,13 +172,15 @@ el_status el_exec_destroy(el_exec ex) {
         if (sl.busy && sl.done) (void)hipEventSynchronize(sl.done);
         release(sl);
         if (sl.done) (void)hipEventDestroy(sl.done);
+        if (sl.ready) (void)hipEventDestroy(sl.ready);
         if (sl.stream) (void)hipStreamDestroy(sl.stream);
     }
     delete ex;
     return EL_OK;
 }
 
-el_status el_exec_start(el_exec ex, el_plan plan, int32_t op, const void *in, void *out, int32_t *slot) {
+el_status el_exec_start(el_exec ex, el_plan plan, int32_t op, const void *in, void *out, void *stream,
+                        int32_t *slot) {
     if (!ex || !plan || !slot) return el::set_error(EL_EINVAL, "executor, plan or slot is NULL");
     *slot = -1;
     if (op != EL_OP_FORWARD && op != EL_OP_ADJOINT) return el::set_error(EL_EINVAL, "op must be EL_OP_FORWARD or EL_OP_ADJOINT");
@@ -192,8 +200,9 @@ el_status el_exec_start(el_exec ex, el_plan plan, int32_t op, const void *in, vo
     if (st != EL_OK) return st;
     ExecSlot &sl = ex->slots[k];
     sl.plan = plan;
-    st = plan->g.precision == EL_F64 ? start_op(ex, sl, plan, plan->dd, op, in, out)
-                                     : start_op(ex, sl, plan, plan->df, op, in, out);
+    const hipStream_t after = reinterpret_cast<hipStream_t>(stream);
+    st = plan->g.precision == EL_F64 ? start_op(ex, sl, plan, plan->dd, op, in, out, after)
+                                     : start_op(ex, sl, plan, plan->df, op, in, out, after);
     if (st != EL_OK) {
         (void)hipStreamSynchronize(sl.stream);
         release(sl);

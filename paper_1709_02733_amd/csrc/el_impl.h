@@ -198,10 +198,13 @@ struct Layout {
     size_t tile_media;       // per tile: lambda, rho, alpha, 0 (elements of the plan's precision)
     size_t tile_lanes;       // per tile and row: 64-bit masks of fluid columns, then of uniform ones
     size_t partial;          // reduction partials
+    size_t energy;           // modified energy: kinetic part of each thread of the tile blocks, then
+                             // kinetic and potential part of each tile block
     size_t total;
 };
 
 constexpr int kDotBlocks = 1024;
+constexpr int kStats = 8;   // media statistics (launch_media_stats)
 
 bool layout(const el_grid &g, int nrec, Layout *L);
 
@@ -217,8 +220,16 @@ template <typename T> hipError_t launch_classify(const Dev<T> &d, const Tiles &t
 template <typename T> hipError_t launch_inject(const Dev<T> &d, const T *p0, hipStream_t s);
 // The forward velocity launch can also gather a trace row (grow != null) from the stresses it
 // reads and does not write: extra blocks after the tiles' run gather_block.
+// epart != null: the launch also writes the kinetic part of the modified energy, one double per
+// thread of every tile block (8 * per * kTileX * kTileY doubles); launch_energy_pot writes the
+// potential part, one double per tile block; launch_energy_final sums the threads' parts per
+// block into kin_block, then everything into *out.
 template <typename T> hipError_t launch_velocity(const Dev<T> &d, const Tiles &tl, hipStream_t s,
-                                                 const Rec *r = nullptr, double *grow = nullptr);
+                                                 const Rec *r = nullptr, double *grow = nullptr,
+                                                 double *epart = nullptr);
+template <typename T> hipError_t launch_energy_pot(const Dev<T> &d, const Tiles &tl, double *epart, hipStream_t s);
+hipError_t launch_energy_final(const double *kin_thread, double *kin_block, const double *pot, int nb, double *out,
+                               hipStream_t s);
 template <typename T> hipError_t launch_stress(const Dev<T> &d, const Tiles &tl, hipStream_t s);
 template <typename T> hipError_t launch_gather(const Dev<T> &d, const Rec &r, double *trace_row, hipStream_t s);
 template <typename T> hipError_t launch_adj_velocity(const Dev<T> &d, const Tiles &tl, hipStream_t s);

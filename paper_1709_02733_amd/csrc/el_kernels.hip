@@ -50,10 +50,11 @@ hipError_t launch_convert_maps(const Dev<T> &d, const float *lam, const float *m
 }
 
 // Media statistics in double: [0] max (lambda+2mu)/rho, [1] min rho, [2] min mu, [3] min lambda+2mu,
-// [4] max dt*alpha, [5] min dt*alpha, [6] count of non-finite values.
+// [4] max dt*alpha, [5] min dt*alpha, [6] count of non-finite values, [7] min 3 lambda + 2 mu (three
+// times the bulk modulus).
 __global__ void k_media_stats_partial(const float *lam, const float *mu, const float *rho, const float *alpha,
                                       long long n, double dt, double *partial) {
-    double v[7] = {0.0, INFINITY, INFINITY, INFINITY, -INFINITY, INFINITY, 0.0};
+    double v[kStats] = {0.0, INFINITY, INFINITY, INFINITY, -INFINITY, INFINITY, 0.0, INFINITY};
     for (long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x; p < n; p += (long long)gridDim.x * blockDim.x) {
         const double l = lam[p], m = mu[p], r = rho[p], a = alpha[p];
         if (!isfinite(l) || !isfinite(m) || !isfinite(r) || !isfinite(a)) v[6] += 1.0;
@@ -64,9 +65,10 @@ __global__ void k_media_stats_partial(const float *lam, const float *mu, const f
         v[3] = fmin(v[3], lm);
         v[4] = fmax(v[4], dt * a);
         v[5] = fmin(v[5], dt * a);
+        v[7] = fmin(v[7], 3.0 * l + 2.0 * m);
     }
-    __shared__ double sh[7][256];
-    for (int q = 0; q < 7; ++q) sh[q][threadIdx.x] = v[q];
+    __shared__ double sh[kStats][256];
+    for (int q = 0; q < kStats; ++q) sh[q][threadIdx.x] = v[q];
     __syncthreads();
     for (int st = 128; st > 0; st >>= 1) {
         if ((int)threadIdx.x < st) {
@@ -78,16 +80,17 @@ __global__ void k_media_stats_partial(const float *lam, const float *mu, const f
             sh[4][t] = fmax(sh[4][t], sh[4][t + st]);
             sh[5][t] = fmin(sh[5][t], sh[5][t + st]);
             sh[6][t] = sh[6][t] + sh[6][t + st];
+            sh[7][t] = fmin(sh[7][t], sh[7][t + st]);
         }
         __syncthreads();
     }
     if (threadIdx.x == 0)
-        for (int q = 0; q < 7; ++q) partial[q * kDotBlocks + blockIdx.x] = sh[q][0];
+        for (int q = 0; q < kStats; ++q) partial[q * kDotBlocks + blockIdx.x] = sh[q][0];
 }
 
 __global__ void k_media_stats_final(const double *partial, int nb, double *stats) {
     if (threadIdx.x != 0) return;
-    double v[7] = {0.0, INFINITY, INFINITY, INFINITY, -INFINITY, INFINITY, 0.0};
+    double v[kStats] = {0.0, INFINITY, INFINITY, INFINITY, -INFINITY, INFINITY, 0.0, INFINITY};
     for (int b = 0; b < nb; ++b) {
         v[0] = fmax(v[0], partial[0 * kDotBlocks + b]);
         v[1] = fmin(v[1], partial[1 * kDotBlocks + b]);
@@ -96,13 +99,14 @@ __global__ void k_media_stats_final(const double *partial, int nb, double *stats
         v[4] = fmax(v[4], partial[4 * kDotBlocks + b]);
         v[5] = fmin(v[5], partial[5 * kDotBlocks + b]);
         v[6] += partial[6 * kDotBlocks + b];
+        v[7] = fmin(v[7], partial[7 * kDotBlocks + b]);
     }
-    for (int q = 0; q < 7; ++q) stats[q] = v[q];
+    for (int q = 0; q < kStats; ++q) stats[q] = v[q];
 }
 
 hipError_t launch_media_stats(const float *lam, const float *mu, const float *rho, const float *alpha, long long n,
                               double dt, double *stats, double *partial, hipStream_t s) {
-    const int nb = 128;   // partial holds 7 * kDotBlocks doubles
+    const int nb = 128;   // partial holds kStats * kDotBlocks doubles
     hipLaunchKernelGGL(k_media_stats_partial, dim3(nb), dim3(256), 0, s, lam, mu, rho, alpha, n, dt, partial);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;

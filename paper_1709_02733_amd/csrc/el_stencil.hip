@@ -207,9 +207,12 @@ __device__ __forceinline__ bool tile_of(const Tiles &tl, int nz, int &x0, int &y
 // written by this pass except that memory variable, which only this lane reads and writes.
 // The adjoint's taps of a psi~ are loaded with the plane's arithmetic, in one batch ahead
 // of its first store (prefetching them too costs more registers than it saves).
-template <typename T, bool ADJ, bool UNI>
+//
+// EN (forward only): also accumulate into kin the kinetic part sum_c rho_c u_old^c u_new^c of
+// the modified energy (Sec. 2.2), with the staggered density of the update itself.
+template <typename T, bool ADJ, bool UNI, bool EN>
 __device__ __forceinline__ void fluid_vel(const Dev<T> &d, int i, int j, int z0, int z1, unsigned o, int t,
-                                          int snx, int sny, int sox, int soy) {
+                                          int snx, int sny, int sox, int soy, double &kin) {
     const T h = d.inv_dx, dt = d.dt;
     const unsigned sx = sizeof(T), sy = d.sy, sz = d.sz;
     const T *s11 = d.f[S11];
@@ -295,6 +298,7 @@ __device__ __forceinline__ void fluid_vel(const Dev<T> &d, int i, int j, int z0,
             out[c] = ADJ ? (T(1) - dt * alp_c) * uold[c] - acc[c] * irho
                          : (T(1) - dt * alp_c) * uold[c] + dt * irho * acc[c];
             stb(d.f[U1 + c], o, out[c]);
+            if (EN) kin += (double)rho_c * (double)uold[c] * (double)out[c];
         }
         rho_k = rho_n[2];
         alp_k = alp_n[2];
@@ -313,10 +317,29 @@ __device__ __forceinline__ void fluid_vel(const Dev<T> &d, int i, int j, int z0,
     }
 }
 
-template <typename T, bool ADJ>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 5 : 1))) void k_vel(Dev<T> d, Tiles tl,
-                                                                                                   Rec r, double *grow) {
+// Sum of v over the block's 256 threads in a fixed order (wavefront butterflies, then the four
+// wavefronts in turn): the same double for the same inputs.  Every thread of the block calls it.
+__device__ __forceinline__ double block_sum(double v) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m);
+    __shared__ double part[NT / 64];
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double s = 0.0;
+#pragma unroll
+    for (int w = 0; w < NT / 64; ++w) s += part[w];
+    return s;
+}
+
+// EN (forward only): each thread also writes its part of the kinetic energy sum (fluid_vel) to
+// epart[blockIdx.x * NT + threadIdx.x], once on every path, padding blocks and lanes outside
+// the grid included (a block reduction would need every lane at a barrier, and the early exits
+// of the plain pass are kept as they are).
+template <typename T, bool ADJ, bool EN>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 5 : 1))) void k_vel(
+    Dev<T> d, Tiles tl, Rec r, double *grow, double *epart) {
     static_assert(NT == 256, "gather_block works on blocks of 256 threads");
+    static_assert(!(ADJ && EN), "the energy belongs to the forward recursion");
     if (!ADJ && grow && (int)blockIdx.x >= 8 * tl.per) {
         // the trace row of the stresses this pass reads (the previous step's), see launch_velocity
         gather_block(d, r, grow, (int)blockIdx.x - 8 * tl.per);
@@ -324,9 +347,17 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
     }
     int x0, y0, z0, z1, t = 0, edges = 0;
     bool fast = false, uni = false, cols = false;
-    if (!tile_of(tl, d.nz, x0, y0, z0, z1, t, fast, uni, cols, edges)) return;
+    double kin = 0.0;
+    double *ekin = EN ? epart + (size_t)blockIdx.x * NT + threadIdx.x : nullptr;
+    if (!tile_of(tl, d.nz, x0, y0, z0, z1, t, fast, uni, cols, edges)) {
+        if (EN) *ekin = kin;
+        return;
+    }
     const int i = x0 + (int)threadIdx.x % TX, j = y0 + (int)threadIdx.x / TX;
-    if (i >= d.nx || j >= d.ny) return;
+    if (i >= d.nx || j >= d.ny) {
+        if (EN) *ekin = kin;
+        return;
+    }
     const T h = d.inv_dx, dt = d.dt;
     const unsigned sx = sizeof(T), sy = d.sy, sz = d.sz;
     const T *s11 = d.f[S11], *s22 = d.f[S22], *s33 = d.f[S33], *s23 = d.f[S23], *s13 = d.f[S13], *s12 = d.f[S12];
@@ -335,14 +366,16 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
     const int snx = pml ? slab_near(i, d.P, d.hi[0]) : -1, sny = pml ? slab_near(j, d.P, d.hi[1]) : -1;
     const int sox = pml ? slab_own(i, d.P, d.hi[0]) : -1, soy = pml ? slab_own(j, d.P, d.hi[1]) : -1;
     if (fast) {
-        if (uni) fluid_vel<T, ADJ, true>(d, i, j, z0, z1, o, t, snx, sny, sox, soy);
-        else fluid_vel<T, ADJ, false>(d, i, j, z0, z1, o, t, snx, sny, sox, soy);
+        if (uni) fluid_vel<T, ADJ, true, EN>(d, i, j, z0, z1, o, t, snx, sny, sox, soy, kin);
+        else fluid_vel<T, ADJ, false, EN>(d, i, j, z0, z1, o, t, snx, sny, sox, soy, kin);
+        if (EN) *ekin = kin;
         return;
     }
     bool fl, ul, rowuni;
     if (fluid_row(tl, t, x0, d.nx, cols, fl, ul, rowuni)) {
-        if (rowuni) fluid_vel<T, ADJ, true>(d, i, j, z0, z1, o, t, snx, sny, sox, soy);
-        else fluid_vel<T, ADJ, false>(d, i, j, z0, z1, o, t, snx, sny, sox, soy);
+        if (rowuni) fluid_vel<T, ADJ, true, EN>(d, i, j, z0, z1, o, t, snx, sny, sox, soy, kin);
+        else fluid_vel<T, ADJ, false, EN>(d, i, j, z0, z1, o, t, snx, sny, sox, soy, kin);
+        if (EN) *ekin = kin;
         return;
     }
     const bool sh = !fl;                     // this lane reads the shear stresses
@@ -457,6 +490,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
             out[c] = ADJ ? (T(1) - dt * alp_c) * uold[c] - acc[c] * irho
                          : (T(1) - dt * alp_c) * uold[c] + dt * irho * acc[c];
             stb(d.f[U1 + c], o, out[c]);
+            if (EN) kin += (double)rho_c * (double)uold[c] * (double)out[c];
         }
         rho_k = rho_n[2];
         alp_k = alp_n[2];
@@ -482,6 +516,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
             }
         }
     }
+    if (EN) *ekin = kin;
 }
 
 // ------------------------------------------------------------------------
@@ -790,10 +825,16 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
 }
 
 template <typename T>
-hipError_t launch_velocity(const Dev<T> &d, const Tiles &tl, hipStream_t s, const Rec *r, double *grow) {
+hipError_t launch_velocity(const Dev<T> &d, const Tiles &tl, hipStream_t s, const Rec *r, double *grow,
+                           double *epart) {
     const bool g = r && grow && r->nrec > 0;
     const int blocks = 8 * tl.per + (g ? gather_blocks(r->nrec) : 0);
-    hipLaunchKernelGGL((k_vel<T, false>), dim3(blocks), dim3(NT), 0, s, d, tl, g ? *r : Rec{}, g ? grow : nullptr);
+    if (epart)
+        hipLaunchKernelGGL((k_vel<T, false, true>), dim3(blocks), dim3(NT), 0, s, d, tl, g ? *r : Rec{},
+                           g ? grow : nullptr, epart);
+    else
+        hipLaunchKernelGGL((k_vel<T, false, false>), dim3(blocks), dim3(NT), 0, s, d, tl, g ? *r : Rec{},
+                           g ? grow : nullptr, (double *)nullptr);
     return hipGetLastError();
 }
 template <typename T>
@@ -803,12 +844,98 @@ hipError_t launch_stress(const Dev<T> &d, const Tiles &tl, hipStream_t s) {
 }
 template <typename T>
 hipError_t launch_adj_velocity(const Dev<T> &d, const Tiles &tl, hipStream_t s) {
-    hipLaunchKernelGGL((k_vel<T, true>), dim3(8 * tl.per), dim3(NT), 0, s, d, tl, Rec{}, (double *)nullptr);
+    hipLaunchKernelGGL((k_vel<T, true, false>), dim3(8 * tl.per), dim3(NT), 0, s, d, tl, Rec{}, (double *)nullptr,
+                       (double *)nullptr);
     return hipGetLastError();
 }
 template <typename T>
 hipError_t launch_adj_stress(const Dev<T> &d, const Tiles &tl, hipStream_t s) {
     hipLaunchKernelGGL((k_str<T, true>), dim3(8 * tl.per), dim3(NT), 0, s, d, tl);
+    return hipGetLastError();
+}
+
+// Potential part of the modified energy (Sec. 2.2): sigma^T C^+ sigma over the stresses of one
+// time level, in double.  At a normal-stress point with moduli lambda, mu
+//   (tr s)^2 / (9 K) + |dev s|^2 / (2 mu),   9 K = 3 (3 lambda + 2 mu),
+// the second term only where mu > 0 (a fluid cell's deviatoric stress stays zero, Sec. 2.1);
+// at a shear point s_ij^2 / mu_ij with the harmonic-mean edge modulus of the stencils, only
+// where it is nonzero.  A fluid tile stores s11 alone (s22 = s33 = s11, shear zero), so its
+// trace is 3 s11 and it has neither deviatoric nor shear part.  Each tile block writes its
+// sum to epart[blockIdx.x].
+template <typename T>
+__device__ __forceinline__ void pot_tile(const Dev<T> &d, const Tiles &tl, double &pot) {
+    int x0, y0, z0, z1, t = 0, edges = 0;
+    bool fast = false, uni = false, cols = false;
+    if (!tile_of(tl, d.nz, x0, y0, z0, z1, t, fast, uni, cols, edges)) return;
+    const int i = x0 + (int)threadIdx.x % TX, j = y0 + (int)threadIdx.x / TX;
+    if (i >= d.nx || j >= d.ny) return;
+    const unsigned sx = sizeof(T), sy = d.sy, sz = d.sz;
+    unsigned o = d.origin + (unsigned)z0 * sz + (unsigned)j * sy + (unsigned)i * sx;
+    for (int k = z0; k < z1; ++k, o += sz) {
+        const double lam = (double)ldb(d.lam, o), mu = (double)ldb(d.mu, o);
+        const double s11 = (double)ldb(d.f[S11], o);
+        if (fast) {
+            const double tr = 3.0 * s11;
+            pot += tr * tr / (3.0 * (3.0 * lam + 2.0 * mu));
+            continue;
+        }
+        const double s22 = (double)ldb(d.f[S22], o), s33 = (double)ldb(d.f[S33], o);
+        const double tr = s11 + s22 + s33;
+        pot += tr * tr / (3.0 * (3.0 * lam + 2.0 * mu));
+        if (mu > 0.0) {
+            const double m = tr / 3.0, a = s11 - m, b = s22 - m, c = s33 - m;
+            pot += (a * a + b * b + c * c) / (2.0 * mu);
+        }
+        // edge moduli: harmonic means of the four cells around each shear point, as the
+        // stencils form them (reciprocals of T, so a zero modulus gives a zero mean)
+        const T r0 = rcp(ldb(d.mu, o)), rx = rcp(ldb(d.mu, o + sx)), ry = rcp(ldb(d.mu, o + sy));
+        const T rz = rcp(ldb(d.mu, o + sz)), rxy = rcp(ldb(d.mu, o + sx + sy));
+        const T rxz = rcp(ldb(d.mu, o + sx + sz)), ryz = rcp(ldb(d.mu, o + sy + sz));
+        const double me[3] = {(double)harmonic4r(r0, ry, rz, ryz), (double)harmonic4r(r0, rx, rz, rxz),
+                              (double)harmonic4r(r0, rx, ry, rxy)};
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            if (!(me[q] > 0.0)) continue;
+            const double sv = (double)ldb(d.f[S23 + q], o);
+            pot += sv * sv / me[q];
+        }
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(NT) void k_energy_pot(Dev<T> d, Tiles tl, double *epart) {
+    double pot = 0.0;
+    pot_tile<T>(d, tl, pot);
+    const double s = block_sum(pot);
+    if (threadIdx.x == 0) epart[blockIdx.x] = s;
+}
+
+template <typename T>
+hipError_t launch_energy_pot(const Dev<T> &d, const Tiles &tl, double *epart, hipStream_t s) {
+    hipLaunchKernelGGL(k_energy_pot<T>, dim3(8 * tl.per), dim3(NT), 0, s, d, tl, epart);
+    return hipGetLastError();
+}
+
+// Per tile block: the sum of its NT per-thread kinetic parts, in a fixed order.
+__global__ __launch_bounds__(NT) void k_energy_blocks(const double *kin_thread, double *kin_block) {
+    const double s = block_sum(kin_thread[(size_t)blockIdx.x * NT + threadIdx.x]);
+    if (threadIdx.x == 0) kin_block[blockIdx.x] = s;
+}
+
+// out = (sum of kin[0..nb) + sum of pot[0..nb)) / 2, in a fixed order.
+__global__ __launch_bounds__(NT) void k_energy_final(const double *kin, const double *pot, int nb, double *out) {
+    double v = 0.0;
+    for (int b = threadIdx.x; b < nb; b += NT) v += kin[b] + pot[b];
+    const double s = block_sum(v);
+    if (threadIdx.x == 0) *out = 0.5 * s;
+}
+
+hipError_t launch_energy_final(const double *kin_thread, double *kin_block, const double *pot, int nb, double *out,
+                               hipStream_t s) {
+    hipLaunchKernelGGL(k_energy_blocks, dim3(nb), dim3(NT), 0, s, kin_thread, kin_block);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_energy_final, dim3(1), dim3(NT), 0, s, kin_block, pot, nb, out);
     return hipGetLastError();
 }
 
@@ -836,7 +963,9 @@ hipError_t launch_fluid_fill(const Dev<T> &d, const Tiles &tl, hipStream_t s) {
 
 #define EL_STENCIL_INST(T)                                                                  \
     template hipError_t launch_fluid_fill<T>(const Dev<T> &, const Tiles &, hipStream_t);   \
-    template hipError_t launch_velocity<T>(const Dev<T> &, const Tiles &, hipStream_t, const Rec *, double *); \
+    template hipError_t launch_velocity<T>(const Dev<T> &, const Tiles &, hipStream_t, const Rec *, double *,  \
+                                           double *);                                                          \
+    template hipError_t launch_energy_pot<T>(const Dev<T> &, const Tiles &, double *, hipStream_t);            \
     template hipError_t launch_stress<T>(const Dev<T> &, const Tiles &, hipStream_t);       \
     template hipError_t launch_adj_velocity<T>(const Dev<T> &, const Tiles &, hipStream_t); \
     template hipError_t launch_adj_stress<T>(const Dev<T> &, const Tiles &, hipStream_t);

@@ -45,7 +45,8 @@ class FluidStats(ctypes.Structure):
 
 _lib = None
 EXPORTS = ("el_version", "el_status_string", "el_last_error", "el_grid_check", "el_plan_bytes",
-           "el_plan_create", "el_plan_destroy", "el_forward", "el_adjoint", "el_dot_f64", "el_eir_apply",
+           "el_plan_create", "el_plan_destroy", "el_forward", "el_forward_energy", "el_adjoint", "el_dot_f64",
+           "el_eir_apply",
            "el_plan_field", "el_plan_layout", "el_plan_sizes", "el_plan_fluid_path", "el_plan_timing",
            "el_plan_kernel_time",
            "el_exec_create", "el_exec_destroy", "el_exec_start", "el_exec_poll", "el_exec_wait", "el_exec_slots")
@@ -75,6 +76,8 @@ def lib():
         L.el_plan_destroy.argtypes = [vp]
         L.el_forward.restype = st
         L.el_forward.argtypes = [vp, vp, vp, vp]
+        L.el_forward_energy.restype = st
+        L.el_forward_energy.argtypes = [vp, vp, vp, i32, vp, vp]
         L.el_adjoint.restype = st
         L.el_adjoint.argtypes = [vp, vp, vp, vp]
         L.el_dot_f64.restype = st
@@ -99,7 +102,7 @@ def lib():
         L.el_exec_destroy.restype = st
         L.el_exec_destroy.argtypes = [vp]
         L.el_exec_start.restype = st
-        L.el_exec_start.argtypes = [vp, vp, i32, vp, vp, ctypes.POINTER(i32)]
+        L.el_exec_start.argtypes = [vp, vp, i32, vp, vp, vp, ctypes.POINTER(i32)]
         L.el_exec_poll.restype = st
         L.el_exec_poll.argtypes = [vp, i32, ctypes.POINTER(i32)]
         L.el_exec_wait.restype = st
@@ -216,6 +219,22 @@ class Plan:
             _check(lib().el_forward(self._h, ctypes.c_void_p(p.data_ptr()), ctypes.c_void_p(out.data_ptr()),
                                     _stream(stream)))
         return out
+
+    def forward_energy(self, p0, every: int = 1, out=None, stream=None):
+        """(traces, energy): traces = H p0 as forward(), and the modified energy E_m (float64,
+        device) of the time levels m = 0, every, ... <= M - 2 (el_forward_energy)."""
+        p = torch.as_tensor(p0).to(device=self.device, dtype=self.dtype).contiguous()
+        assert p.numel() == self.N
+        if out is None:
+            out = torch.empty((self.nsteps, self.nrec), dtype=torch.float64, device=self.device)
+        assert out.dtype == torch.float64 and out.is_contiguous() and out.numel() == self.nsteps * self.nrec
+        every = int(every)
+        ne = (self.nsteps - 1 + every - 1) // every if self.nsteps > 1 and every >= 1 else 0
+        energy = torch.empty(max(ne, 1), dtype=torch.float64, device=self.device)
+        with torch.cuda.device(self.device):
+            _check(lib().el_forward_energy(self._h, ctypes.c_void_p(p.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                           every, ctypes.c_void_p(energy.data_ptr()), _stream(stream)))
+        return out, energy[:ne]
 
     def adjoint(self, y, out=None, stream=None) -> torch.Tensor:
         """p_adj[nz][ny][nx] (plan precision, device) = H^T y."""
@@ -338,11 +357,13 @@ class Executor:
         self.max_slots = int(max_slots)
         self._held = {}
 
-    def start(self, plan: "Plan", op: int, inp: torch.Tensor, out: torch.Tensor) -> int:
+    def start(self, plan: "Plan", op: int, inp: torch.Tensor, out: torch.Tensor, stream=None) -> int:
+        """The operation is ordered after the work enqueued so far on `stream` (default: the
+        current torch stream, which wrote inp)."""
         slot = ctypes.c_int32(-1)
         with torch.cuda.device(self.device):
             _check(lib().el_exec_start(self._h, plan._h, int(op), ctypes.c_void_p(inp.data_ptr()),
-                                       ctypes.c_void_p(out.data_ptr()), ctypes.byref(slot)))
+                                       ctypes.c_void_p(out.data_ptr()), _stream(stream), ctypes.byref(slot)))
         self._held[slot.value] = (plan, inp, out)
         return slot.value
 

@@ -88,3 +88,22 @@ def test_grid_check_rejects_arrays_beyond_32bit_offsets():
     assert ei.value.status == el.EL_EINVAL
     with pytest.raises(el.ElError):
         el.grid_check(el.make_grid(820, 820, 820, 1e-4, 1e-8, 10, 16, precision="f64"))   # 4.5 GiB in double
+
+
+def test_grid_check_rejects_slabs_beyond_32bit_offsets():
+    # thin grids: a C-PML memory-variable slab (2 (P + 7) planes of nx * ny cells along z) can
+    # outgrow the volume arrays; its 32-bit byte offsets must not wrap
+    with pytest.raises(el.ElError) as ei:
+        el.grid_check(el.make_grid(8000, 8000, 10, 1e-4, 1e-8, 10, 4))        # 22 * 8000^2 * 4 B = 5.6 GB
+    assert ei.value.status == el.EL_EINVAL and "C-PML" in str(ei.value)
+    with pytest.raises(el.ElError) as ei:
+        el.grid_check(el.make_grid(11000, 11000, 4, 1e-4, 1e-8, 10, 1))       # 16 * 11000^2 * 4 B = 7.7 GB
+    assert ei.value.status == el.EL_EINVAL
+    # just inside: 22 * 6900^2 * 4 B = 4.19e9 < 2^32, volumes 2.7 GB
+    el.grid_check(el.make_grid(6900, 6900, 10, 1e-4, 1e-8, 10, 4))
+    assert el.plan_bytes(el.make_grid(6900, 6900, 10, 1e-4, 1e-8, 10, 4), 1) > 0
+    # the same thin grid without a C-PML has no slabs and is accepted
+    el.grid_check(el.make_grid(8000, 8000, 10, 1e-4, 1e-8, 10, 0))
+    # in double the limit halves
+    with pytest.raises(el.ElError):
+        el.grid_check(el.make_grid(6900, 6900, 10, 1e-4, 1e-8, 10, 4, precision="f64"))

@@ -78,6 +78,7 @@ def test_parity64_forward_and_adjoint(parity64):
     banner(f"parity64 rel L2 traces {e_tr:.3e} adjoint {e_pa:.3e}")
     assert e_tr <= TOL32 and e_pa <= TOL32
     assert rel_max(tr, tr_ref) <= TOL32
+    assert rel_max(pa, pa_ref) <= TOL32
 
 
 def _dot_residual(plan, sc, seed):
@@ -363,6 +364,14 @@ def test_plan_rejects_unstable_and_invalid_media():
     with pytest.raises(el.ElError) as ei:
         _plan(sc, lam=lam)
     assert ei.value.status == el.EL_EINVAL
+    # a zero or negative bulk modulus (3 lambda + 2 mu <= 0) with lambda + 2 mu > 0
+    for lam_v, mu_v in ((-2.0e9, 3.0e9), (-0.8e9, 1.0e9)):
+        lam, mu = sc.lam.copy(), sc.mu.copy()
+        lam[4, 5, 6], mu[4, 5, 6] = lam_v, mu_v
+        assert lam_v + 2 * mu_v > 0 and 3 * lam_v + 2 * mu_v <= 0
+        with pytest.raises(el.ElError) as ei:
+            _plan(sc, lam=lam, mu=mu)
+        assert ei.value.status == el.EL_EINVAL and "3 lambda + 2 mu" in str(ei.value)
     # the plan still works after rejected attempts
     plan = _plan(sc)
     assert torch.isfinite(plan.forward(torch.from_numpy(sc.p0))).all()

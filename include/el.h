@@ -184,6 +184,29 @@ el_status el_adjoint(el_plan plan, const double *y, void *p_adj, void *stream);
 el_status el_dot_f64(el_plan plan, int32_t space, const void *a, const void *b, double *out, void *stream);
 
 /*
+ * *out = <a, b> accumulated in double, as el_dot_f64 computes it (the same
+ * kernels and reduction order, so the same double), without a plan and
+ * without any device memory from the caller beyond a, b and out.  For
+ * callers that cannot allocate device memory: code under stream capture,
+ * tight serving loops, harnesses that forbid hipMalloc.  The library calls
+ * no allocating routine here; the partial sums live in a static device
+ * array of the library (8 KiB per GPU, kept until the process ends), whose
+ * address is looked up on the first call on each device.
+ *   precision: EL_F32 (a, b hold floats) or EL_F64 (doubles).
+ *   n: element count, 0 .. 2^40 (the partial sums are a fixed 1024 doubles
+ *      whatever n is; a, b may be NULL when n = 0, which gives 0).
+ *   a, b, out (device): n elements each; one double.
+ * Every call on a GPU shares that GPU's array: calls that overlap in time
+ * on one GPU (different streams, or different host threads) race and may
+ * return wrong sums; calls ordered on one stream do not.  Nothing in the
+ * array needs clearing: each call writes every partial sum before reading it.
+ * Asynchronous on `stream`.  Errors: EL_EINVAL for a precision other than
+ * EL_F32 / EL_F64, n outside 0 .. 2^40, or a NULL out (or a, b with n > 0);
+ * EL_EDEVICE if the array's address cannot be obtained.
+ */
+el_status el_dot_f64_noalloc(int32_t precision, int64_t n, const void *a, const void *b, double *out, void *stream);
+
+/*
  * Transducer response.  The recorded signal is the pressure at the
  * transducer convolved in time with the transducer's electrical impulse
  * response (Sec. 2.3, the imaging model with the transducer's temporal

@@ -46,7 +46,7 @@ class FluidStats(ctypes.Structure):
 _lib = None
 EXPORTS = ("el_version", "el_status_string", "el_last_error", "el_grid_check", "el_plan_bytes",
            "el_plan_create", "el_plan_destroy", "el_forward", "el_forward_energy", "el_adjoint", "el_dot_f64",
-           "el_eir_apply",
+           "el_dot_f64_noalloc", "el_eir_apply",
            "el_plan_field", "el_plan_layout", "el_plan_sizes", "el_plan_fluid_path", "el_plan_timing",
            "el_plan_kernel_time",
            "el_exec_create", "el_exec_destroy", "el_exec_start", "el_exec_poll", "el_exec_wait", "el_exec_slots")
@@ -82,6 +82,8 @@ def lib():
         L.el_adjoint.argtypes = [vp, vp, vp, vp]
         L.el_dot_f64.restype = st
         L.el_dot_f64.argtypes = [vp, i32, vp, vp, vp, vp]
+        L.el_dot_f64_noalloc.restype = st
+        L.el_dot_f64_noalloc.argtypes = [i32, ctypes.c_int64, vp, vp, vp, vp]
         L.el_eir_apply.restype = st
         L.el_eir_apply.argtypes = [vp, i32, vp, vp, i32, i32, i32, vp]
         L.el_plan_field.restype = st
@@ -305,6 +307,21 @@ class Plan:
         flat = self.workspace[off:off + cnt.value * es].view(self.dtype)
         nz, ny, nx = self.shape
         return flat.as_strided((nz, ny, nx), (pl.value, px.value, 1), flat.storage_offset() + org.value)
+
+
+def dot_noalloc(a: torch.Tensor, b: torch.Tensor, out=None, stream=None) -> torch.Tensor:
+    """<a, b> in float64 on the device without a plan or device allocation by the library
+    (el_dot_f64_noalloc); a, b are contiguous float32 or float64 device tensors of equal size."""
+    if a.dtype != b.dtype or a.dtype not in (torch.float32, torch.float64) or a.numel() != b.numel():
+        raise ValueError("a and b must be float32 or float64 tensors of one dtype and size")
+    if not (a.is_cuda and b.is_cuda and a.is_contiguous() and b.is_contiguous()):
+        raise ValueError("a and b must be contiguous device tensors")
+    if out is None:
+        out = torch.empty((), dtype=torch.float64, device=a.device)
+    prec = EL_F64 if a.dtype == torch.float64 else EL_F32
+    _check(lib().el_dot_f64_noalloc(prec, a.numel(), ctypes.c_void_p(a.data_ptr()), ctypes.c_void_p(b.data_ptr()),
+                                    ctypes.c_void_p(out.data_ptr()), _stream(stream)))
+    return out
 
 
 def eir_apply(h: torch.Tensor, traces: torch.Tensor, transpose: bool = False, out=None, stream=None) -> torch.Tensor:

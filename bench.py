@@ -73,31 +73,100 @@ def cpu_model() -> str:
     return platform.processor() or "unknown"
 
 
-def cpu_baseline(sc, sample_steps: int):
-    """FP64 oracle on the same grid and medium: (sample_steps - 1) forward and as many
-    adjoint updates, reported in Gcell-updates/s."""
+def lscpu_model() -> str:
+    """The CPU model as lscpu names it (falls back to /proc/cpuinfo)."""
+    import subprocess
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                return line.split(":", 1)[1].strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    return cpu_model()
+
+
+def _omp_set_threads(n: int) -> None:
+    """Thread count of the oracle's later OpenMP parallel regions (libgomp's own setter)."""
+    import ctypes
+    ctypes.CDLL("libgomp.so.1").omp_set_num_threads(int(n))
+
+
+def _time_ops(m, p0, y, nsteps: int, repeats: int, warmup: bool):
+    """Best wall time of the oracle's forward and adjoint (timed separately) over `repeats`
+    runs, after one untimed run of each when warmup is set."""
+    if warmup:
+        m.forward(p0, nsteps=nsteps)
+        m.adjoint(y, nsteps=nsteps)
+    tf, ta = [], []
+    for _ in range(repeats):
+        t0 = time.perf_counter()
+        m.forward(p0, nsteps=nsteps)
+        t1 = time.perf_counter()
+        m.adjoint(y, nsteps=nsteps)
+        t2 = time.perf_counter()
+        tf.append(t1 - t0)
+        ta.append(t2 - t1)
+    return min(tf), min(ta)
+
+
+def cpu_baseline(sc, full: bool):
+    """The FP64 stencil oracle (plain C, OpenMP over z) on the host cores.
+
+    Main figure (`value`): the benchmark's own workload sc on every host core, a bounded
+    sample of 2 forward and 2 adjoint updates (one run each).  Beside it, the 64^3 /
+    400-sample parity workload (water with a solid spherical shell, 3 balls, 128
+    receivers), forward and adjoint timed separately, best of 3 after one warm-up, on every
+    host core, and a one-thread sample of that grid (29 updates each way, one run).  With
+    `full`, the 96^3 / 600-sample skull cross-check as well, on every core and on one
+    thread (best of 3 after a warm-up each)."""
     import numpy as np
     from oracle import oracle as O
-    t0 = time.time()
-    m = O.Model.from_scenario(sc)
-    log(f"[cpu] oracle model built in {time.time() - t0:.1f}s, threads {O.num_threads()}")
-    p0 = sc.p0.astype(np.float64)
+    from paper_1709_02733_amd import scenarios as S
+
+    ncores = os.cpu_count() or 1
+    host = {"nproc": ncores, "lscpu_model": lscpu_model(), "OMP_NUM_THREADS": os.environ.get("OMP_NUM_THREADS")}
+
+    def measure(sc, nsteps, threads, repeats, warmup):
+        _omp_set_threads(threads)
+        m = O.Model.from_scenario(sc)
+        p0 = sc.p0.astype(np.float64)
+        y = m.forward(p0, nsteps=nsteps)
+        used = O.num_threads()
+        tf, ta = _time_ops(m, p0, y, nsteps, repeats, warmup)
+        upd = sc.ncells * (nsteps - 1)
+        r = {"workload": f"{sc.name} {sc.nx}x{sc.ny}x{sc.nz}, M={nsteps}", "threads": used,
+             "forward_s": tf, "adjoint_s": ta, "forward_gcells": upd / tf / 1e9, "adjoint_gcells": upd / ta / 1e9,
+             "both_gcells": 2 * upd / (tf + ta) / 1e9,
+             "timing": f"best of {repeats}" + (" after one warm-up" if warmup else ", no warm-up")}
+        log(f"[cpu] {r['workload']} threads {used}: forward {tf:.2f}s ({r['forward_gcells']:.4f} Gcell/s), "
+            f"adjoint {ta:.2f}s ({r['adjoint_gcells']:.4f} Gcell/s)")
+        return r
+
     t0 = time.perf_counter()
-    tr = m.forward(p0, nsteps=sample_steps)
-    t1 = time.perf_counter()
-    m.adjoint(tr, nsteps=sample_steps)
-    t2 = time.perf_counter()
-    updates = 2 * sc.ncells * (sample_steps - 1)
-    log(f"[cpu] forward {t1 - t0:.1f}s adjoint {t2 - t1:.1f}s")
+    main_r = measure(sc, 3, ncores, 1, False)
+    c1 = S.make("parity64")
+    runs = [main_r, measure(c1, c1.nsteps, ncores, 3, True), measure(c1, 30, 1, 1, False)]
+    if full:
+        c3 = S.make("skull96")
+        runs.append(measure(c3, c3.nsteps, ncores, 3, True))
+        runs.append(measure(c3, c3.nsteps, 1, 3, True))
+    _omp_set_threads(ncores)
     return {
-        "value": updates / (t2 - t0) / 1e9,
+        "value": main_r["both_gcells"],
         "unit": "Gcell-updates/s",
-        "cores": O.num_threads(),
+        "cores": main_r["threads"],
         "kind": "oracle",
-        "sample": (f"{sc.nx}x{sc.ny}x{sc.nz} skull medium, {sample_steps - 1} forward + {sample_steps - 1} "
-                   f"adjoint updates (FP64 stencil oracle, OpenMP), {updates:.3e} cell-updates"),
-        "cpu": cpu_model(),
-        "seconds": t2 - t0,
+        "sample": (f"{sc.nx}x{sc.ny}x{sc.nz} benchmark workload, 2 forward + 2 adjoint updates (one run each, "
+                   f"{4 * sc.ncells:.3e} cell-updates) on {main_r['threads']} OpenMP threads; runs[1]: the 64^3 / "
+                   f"400-sample parity workload, forward and adjoint timed separately, best of 3 after a warm-up, "
+                   f"all threads; runs[2]: one thread on that grid (29 updates each way)"
+                   + ("; runs[3:5]: the 96^3 / 600-sample skull cross-check on all threads and on one thread"
+                      if full else "")),
+        "cpu": host["lscpu_model"],
+        "host": host,
+        "runs": runs,
+        "seconds": time.perf_counter() - t0,
     }
 
 
@@ -111,8 +180,12 @@ def main():
     ap.add_argument("--timing-every", type=int, default=10,
                     help="bracket the kernel launches of every n-th time step with HIP events (1: all)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-sample-steps", type=int, default=3)
+    ap.add_argument("--cpu-full", action="store_true",
+                    help="also time the oracle on the 96^3 / 600-sample cross-check (all cores and one thread; "
+                         "several minutes)")
     ap.add_argument("--no-serving", action="store_true", help="skip the plain vs batched serving comparison")
+    ap.add_argument("--no-general", action="store_true",
+                    help="skip the general-update measurement (the workload with the fluid update off)")
     ap.add_argument("--serving-rates", type=float, nargs="+", default=[2.0, 10.0])
     ap.add_argument("--serving-count", type=int, default=16)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -207,6 +280,46 @@ def main():
                                        skipped, uniform) for op in ("fwd", "adj")) * (sc.nsteps - 1)
     whole_gbs = step_gb * args.steps / (total_ms / 1e3) / 1e9
 
+    general = None
+    if not args.no_general:
+        # the same workload with the fluid update off: every cell takes the general (elastic)
+        # update, whose algorithmic bytes are the dense model's (136 B forward, 142 B adjoint
+        # per cell-update at this C-PML thickness)
+        plan.fluid_path(False)
+        plan.forward(p0, out=traces)          # one untimed operation in the new tile order
+        torch.cuda.synchronize()
+        plan.timing(True, every=args.timing_every)
+        g0, g1, g2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        g0.record()
+        plan.forward(p0, out=traces)
+        g1.record()
+        plan.adjoint(traces, out=padj)
+        g2.record()
+        torch.cuda.synchronize()
+        plan.timing(False)
+        gk = plan.kernel_times()
+        plan.fluid_path(True)
+        gf_ms, ga_ms = g0.elapsed_time(g1), g1.elapsed_time(g2)
+        gper = {}
+        for name, (n, ms) in gk.items():
+            if n == 0:
+                continue
+            b = bytemodel.kernel_bytes(name, sc.nx, sc.ny, sc.nz, sc.npml, sc.nrec, 4, 0, 0, 0, 0)
+            avg = ms / n
+            gper[name] = {"avg_us": avg * 1e3, "gbs": b / (avg / 1e3) / 1e9, "launches": n,
+                          "bytes_per_launch": b, "frac": b / (avg / 1e3) / 1e9 / HBM_PEAK_GBS}
+            log(f"[bench] general {name:13s} {n:6d} launches  avg {avg * 1e3:9.2f} us  {gper[name]['gbs']:8.1f} GB/s")
+        gdom = max(gper, key=lambda k: gper[k]["avg_us"] * gper[k]["launches"])
+        general = {"value": 2 * upd / ((gf_ms + ga_ms) / 1e3) / 1e9, "unit": "Gcell-updates/s",
+                   "fwd_gcells": upd / (gf_ms / 1e3) / 1e9, "adj_gcells": upd / (ga_ms / 1e3) / 1e9,
+                   "ms_per_step": gf_ms + ga_ms, "steps": 1,
+                   "byte_model": "dense: every cell at the general update's bytes",
+                   "roofline": {"bound": "hbm", "kernel": gdom, "achieved": gper[gdom]["gbs"], "peak": HBM_PEAK_GBS,
+                                "unit": "GB/s", "frac": gper[gdom]["frac"]},
+                   "kernels": gper}
+        log(f"[bench] general update only: forward {gf_ms:.1f} ms, adjoint {ga_ms:.1f} ms, "
+            f"{general['value']:.1f} Gcell-updates/s")
+
     serving = None
     if not args.no_serving:
         from paper_1709_02733_amd import serving as SV
@@ -225,7 +338,7 @@ def main():
     cpu = None
     if not args.no_cpu:
         torch.cuda.empty_cache()
-        cpu = cpu_baseline(sc, args.cpu_sample_steps)
+        cpu = cpu_baseline(sc, args.cpu_full)
 
     out = {
         "metric": METRIC,
@@ -252,6 +365,7 @@ def main():
         "whole_step_gbs": whole_gbs,
         "roofline": roofline,
         "kernels": {k: {"avg_us": v["avg_us"], "gbs": v["gbs"], "launches": v["launches"]} for k, v in per.items()},
+        "general_path": general,
         "serving": serving,
         "cpu_baseline": cpu,
     }

@@ -266,9 +266,10 @@ el_status el_plan_sizes(el_plan plan, int64_t *ncells, int32_t *nrec, int32_t *n
  * a per-tile table instead of the maps, again with the same results.
  * Inside the other tiles, every column of 1 x 1 cells by the chunk whose
  * cells within two have mu = 0 is marked too and takes the fluid update,
- * storing all three normal stresses: a row of such columns runs the fluid
- * loop, and in a row that also holds other columns the fluid lanes run the
- * general loop without the loads they do not need (shear stresses, moduli).
+ * storing all three normal stresses: a wavefront (32 x 2 cells of the tile)
+ * of such columns runs the fluid loop, and in a wavefront that also holds
+ * other columns the fluid lanes run the general loop without the loads they
+ * do not need (shear stresses, moduli).
  * A column whose box holds the tile's reference medium (that of its first
  * fluid column) takes it from the table as well.
  */

@@ -26,7 +26,7 @@
 // difference of In is evaluated as dt D[w] (or dt D[r]) plus, only where a
 // tap reaches a C-PML slab of that axis, D[g] on the extended slab planes.
 //
-// Tiling: a block owns a 64 x 4 column tile (one wavefront per row) and each
+// Tiling: a block owns a 64 x 4 column tile (four wavefronts of 32 x 2 cells) and each
 // thread marches along z through a chunk of planes of its own column.
 // Inputs differentiated along z sit in four-deep register queues; taps along
 // x and y are read from memory, where the neighbouring rows of the tile and
@@ -49,9 +49,9 @@
 // entry), s11 everywhere; k_fluid_fill restores s22 = s33 = s11 on fluid tiles
 // at the end of an operation.  Fluid tiles of uniform media take lambda, rho
 // and alpha from a per-tile table.  Inside the other tiles, fluid columns are
-// marked per lane: a row of fluid columns runs the lean loop, and the fluid
-// lanes of a mixed row run the general loop with the loads they do not need
-// masked off.  The results are those of the general loop.
+// marked per lane: a wavefront of fluid columns runs the lean loop, and the
+// fluid lanes of a mixed wavefront run the general loop with the loads they do
+// not need masked off.  The results are those of the general loop.
 #include "el_impl.h"
 
 namespace el {
@@ -85,24 +85,54 @@ __device__ __forceinline__ T ld_or(bool on, const T *base, unsigned off, T alt) 
     return v;
 }
 
+// Cells of a wavefront.  A tile's four wavefronts each cover kWaveX columns of kWaveY rows
+// (32 x 2): one 128-byte line of each of two rows per load, as coalesced as a 64 x 1 row,
+// while a wavefront that meets a solid region holds half as many fluid columns that must run
+// the general loop with it (the shell of the skull medium crosses most 64-wide rows of the
+// tiles it touches).
+constexpr int kWaveX = 32;
+constexpr int kWaveY = 64 / kWaveX;
+static_assert(TX % kWaveX == 0 && TY % kWaveY == 0 && (TX / kWaveX) * (TY / kWaveY) == NT / 64,
+              "a tile is covered by its wavefronts");
+// Column (i - x0) and row (j - y0) of this thread's cell within its tile.
+__device__ __forceinline__ int tile_col() {
+    return ((int)threadIdx.x >> 6) % (TX / kWaveX) * kWaveX + ((int)threadIdx.x & 63) % kWaveX;
+}
+__device__ __forceinline__ int tile_row() {
+    return ((int)threadIdx.x >> 6) / (TX / kWaveX) * kWaveY + ((int)threadIdx.x & 63) / kWaveX;
+}
+
 // Fluid columns of a general tile (Tiles::lanes).  fl: this lane's column is fluid; ul: its
 // lambda, rho and alpha are the tile's reference medium (in the per-tile table).  Returns
-// true for a row whose columns are all fluid, which runs the fluid loop (uniform when every
-// column is, rowuni); in a mixed row the fluid lanes run the general loop with the loads they
-// do not need masked off (their shear taps are zero, and s22 = s33 = s11 on their taps).
-__device__ __forceinline__ bool fluid_row(const Tiles &tl, int t, int x0, int nx, bool cols, bool &fl, bool &ul,
-                                          bool &rowuni) {
+// true for a wavefront whose columns inside the grid are all fluid, which runs the fluid loop
+// (uniform when every such column is, rowuni); in a mixed wavefront the fluid lanes run the
+// general loop with the loads they do not need masked off (their shear taps are zero, and
+// s22 = s33 = s11 on their taps).
+__device__ __forceinline__ bool fluid_row(const Tiles &tl, int t, int x0, int y0, int nx, int ny, bool cols, bool &fl,
+                                          bool &ul, bool &rowuni) {
     fl = ul = rowuni = false;
     if (!cols) return false;
-    const int row = (int)threadIdx.x / TX, lane = (int)threadIdx.x % TX;
-    const unsigned long long m = tl.lanes[kTileY * t + row];
-    const unsigned long long um = tl.lanes[kTileY * ((size_t)tl.ntiles + t) + row];
+    const int col = tile_col(), row = tile_row();
+    const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);   // uniform: scalar mask loads
+    const int wx = wave % (TX / kWaveX), wy = wave / (TX / kWaveX);
     const int nv = min(TX, nx - x0);
-    const unsigned long long valid = nv >= 64 ? ~0ull : ((1ull << nv) - 1ull);
-    fl = ((m >> lane) & 1ull) != 0;
-    ul = ((um >> lane) & 1ull) != 0;
-    rowuni = (um & valid) == valid;
-    return (m & valid) == valid;
+    const unsigned long long inx = nv >= 64 ? ~0ull : ((1ull << nv) - 1ull);
+    const unsigned long long seg = (kWaveX == 64 ? ~0ull : ((1ull << kWaveX) - 1ull)) << (wx * kWaveX);
+    bool all = true, alluni = true;
+#pragma unroll
+    for (int r = wy * kWaveY; r < (wy + 1) * kWaveY; ++r) {
+        const unsigned long long m = tl.lanes[kTileY * t + r];
+        const unsigned long long um = tl.lanes[kTileY * ((size_t)tl.ntiles + t) + r];
+        const unsigned long long valid = y0 + r < ny ? (inx & seg) : 0ull;
+        all = all && (m & valid) == valid;
+        alluni = alluni && (um & valid) == valid;
+        if (r == row) {
+            fl = ((m >> col) & 1ull) != 0;
+            ul = ((um >> col) & 1ull) != 0;
+        }
+    }
+    rowuni = alluni;
+    return all;
 }
 
 // 4th-order staggered differences (Sec. 2.2, eq. derivative):
@@ -353,7 +383,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
         if (EN) *ekin = kin;
         return;
     }
-    const int i = x0 + (int)threadIdx.x % TX, j = y0 + (int)threadIdx.x / TX;
+    const int i = x0 + tile_col(), j = y0 + tile_row();
     if (i >= d.nx || j >= d.ny) {
         if (EN) *ekin = kin;
         return;
@@ -372,7 +402,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
         return;
     }
     bool fl, ul, rowuni;
-    if (fluid_row(tl, t, x0, d.nx, cols, fl, ul, rowuni)) {
+    if (fluid_row(tl, t, x0, y0, d.nx, d.ny, cols, fl, ul, rowuni)) {
         if (rowuni) fluid_vel<T, ADJ, true, EN>(d, i, j, z0, z1, o, t, snx, sny, sox, soy, kin);
         else fluid_vel<T, ADJ, false, EN>(d, i, j, z0, z1, o, t, snx, sny, sox, soy, kin);
         if (EN) *ekin = kin;
@@ -383,9 +413,9 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
                                              // adjoint has no registers to spare for the choice)
     const T rho_t = d.med[4 * t + 1], alp_t = d.med[4 * t + 2];
     // s22 and s33 hold s11's value on a fluid lane's taps (fluid columns store all three,
-    // fluid tiles the bands next to general tiles); the forward pass reads them from s11,
-    // the adjoint, with no registers to spare for per-lane pointers, from their own arrays
-    const T *p22 = fl && !ADJ ? s11 : s22, *p33 = fl && !ADJ ? s11 : s33;
+    // fluid tiles the bands next to general tiles), so every lane reads them from their own
+    // arrays (a per-lane choice of array would cost registers this loop does not have)
+    const T *p22 = s22, *p33 = s33;
     T qa[4], qb[4], qc[4];   // s13, s23 at planes k-2..k+1; s33 at planes k-1..k+2
     qa[0] = qb[0] = qc[0] = T(0);
     qa[1] = ld_if(sh, s13, o - 2 * sz);
@@ -649,7 +679,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
     int x0, y0, z0, z1, t = 0, edges = 0;
     bool fast = false, uni = false, cols = false;
     if (!tile_of(tl, d.nz, x0, y0, z0, z1, t, fast, uni, cols, edges)) return;
-    const int i = x0 + (int)threadIdx.x % TX, j = y0 + (int)threadIdx.x / TX;
+    const int i = x0 + tile_col(), j = y0 + tile_row();
     if (i >= d.nx || j >= d.ny) return;
     const T h = d.inv_dx, dt = d.dt;
     const unsigned sx = sizeof(T), sy = d.sy, sz = d.sz;
@@ -664,16 +694,16 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
         return;
     }
     bool fl, ul, rowuni;
-    const bool row = fluid_row(tl, t, x0, d.nx, cols, fl, ul, rowuni);
+    const bool row = fluid_row(tl, t, x0, y0, d.nx, d.ny, cols, fl, ul, rowuni);
     if (row || (ADJ && fl)) {
-        // fluid row of a general tile (or, in the adjoint, whose general loop has no registers
-        // to spare for the masked loads, a fluid lane of a mixed row; the row then executes
-        // both loops): its neighbours read s22 and s33, so all are stored
+        // fluid wavefront of a general tile (or, in the adjoint, whose general loop has no
+        // registers to spare for the masked loads, a fluid lane of a mixed wavefront, which
+        // then executes both loops): its neighbours read s22 and s33, so all are stored
         if (row && rowuni) fluid_str<T, ADJ, true>(d, i, j, y0, z0, z1, o, t, 0, true, true, snx, sny, sox, soy);
         else fluid_str<T, ADJ, false>(d, i, j, y0, z0, z1, o, t, 0, true, ul, snx, sny, sox, soy);
         return;
     }
-    // A fluid lane of a mixed row needs only the normal strains: the shear-strain taps and
+    // A fluid lane of a mixed wavefront needs only the normal strains: the shear-strain taps and
     // the moduli read as zero (their true values on this lane's cell and taps), the shear
     // stresses are neither read nor written, and s22 = s33 = s11 is read from s11.
     const bool sh = !fl;
@@ -867,7 +897,7 @@ __device__ __forceinline__ void pot_tile(const Dev<T> &d, const Tiles &tl, doubl
     int x0, y0, z0, z1, t = 0, edges = 0;
     bool fast = false, uni = false, cols = false;
     if (!tile_of(tl, d.nz, x0, y0, z0, z1, t, fast, uni, cols, edges)) return;
-    const int i = x0 + (int)threadIdx.x % TX, j = y0 + (int)threadIdx.x / TX;
+    const int i = x0 + tile_col(), j = y0 + tile_row();
     if (i >= d.nx || j >= d.ny) return;
     const unsigned sx = sizeof(T), sy = d.sy, sz = d.sz;
     unsigned o = d.origin + (unsigned)z0 * sz + (unsigned)j * sy + (unsigned)i * sx;
@@ -945,7 +975,7 @@ __global__ __launch_bounds__(NT) void k_fluid_fill(Dev<T> d, Tiles tl) {
     int x0, y0, z0, z1, t = 0, edges = 0;
     bool fast = false, uni = false, cols = false;
     if (!tile_of(tl, d.nz, x0, y0, z0, z1, t, fast, uni, cols, edges) || !fast) return;
-    const int i = x0 + (int)threadIdx.x % TX, j = y0 + (int)threadIdx.x / TX;
+    const int i = x0 + tile_col(), j = y0 + tile_row();
     if (i >= d.nx || j >= d.ny) return;
     unsigned o = d.origin + (unsigned)z0 * d.sz + (unsigned)j * d.sy + (unsigned)i * (unsigned)sizeof(T);
     for (int k = z0; k < z1; ++k, o += d.sz) {

@@ -52,6 +52,16 @@
  *    d0 = -(n+1) c_max ln(R) / (2 P dx), beta = pi f0 (1 - xi),
  *    xi = depth into the layer / P clamped to [0,1], measured from the inner
  *    planes P and n-1-P; b = exp(-(d+beta) dt), a = d/(d+beta) (b-1).
+ *
+ * Frequency-dependent absorption (the extension the conclusion, Sec. 8, asks
+ * for, of the velocity damping alpha u of Sec. 2.1 eq. subeq1): optional
+ * relaxation mechanisms add sum_l beta_l (u - zeta_l) to the damping, with
+ * d/dt zeta_l = omega_l (u - zeta_l), i.e. a damping rate
+ *   a(omega) = alpha + sum_l beta_l i omega / (omega_l + i omega)
+ * that grows with frequency.  Discretely, a pointwise sub-update R follows the
+ * velocity update (2) of every step (relax_matrix); the adjoint step applies
+ * R^T, the transpose of the same matrix, at the mirrored place.  The memory
+ * variables zeta_l extend the state after the paper's 27N entries.
  */
 #include <math.h>
 #include <stdint.h>
@@ -84,7 +94,16 @@ typedef struct {
     int64_t *rbase;           /* [L][8] cell indices of the 8 trilinear corners */
     double *rw;               /* [L][8] weights                                */
     int32_t *coord[3];        /* x, y, z index of every grid point             */
+    /* frequency-dependent absorption (relaxation mechanisms l = 0..nmech-1):
+       damping alpha u + sum_l beta_l (u - zeta_l), d/dt zeta_l = omega_l (u - zeta_l),
+       beta_l = w_l * beta_u; zeta_l stored after the 27N state, 3 arrays per mechanism */
+    int nmech;
+    double mech_w[4], mech_c[4];   /* weights w_l and c_l = exp(-omega_l dt)        */
+    double *beta_u[3];        /* relaxation strength at u^i points (NULL if nmech = 0) */
 } eo_model;
+
+/* Length of the state vector: the 27N of the Appendix plus 3N per relaxation mechanism. */
+static int64_t state_len(const eo_model *m) { return (int64_t)(27 + 3 * m->nmech) * m->N; }
 
 /* ---------------------------------------------------------------- helpers */
 
@@ -170,6 +189,7 @@ typedef struct {
     double *u[3];
     double *psi[3][3];
     double *sig[6];
+    double *zeta[4][3];       /* relaxation memory variables [mechanism][component] */
 } eo_view;
 
 static eo_view view(const eo_model *m, double *v) {
@@ -181,7 +201,52 @@ static eo_view view(const eo_model *m, double *v) {
     for (int i = 0; i < 3; ++i)
         for (int j = 0; j < 3; ++j) s.psi[i][j] = v + (12 + 3 * i + j) * N;
     for (int a = 0; a < 6; ++a) s.sig[a] = v + (21 + a) * N;
+    for (int l = 0; l < 4; ++l)
+        for (int i = 0; i < 3; ++i) s.zeta[l][i] = l < m->nmech ? v + (27 + 3 * l + i) * N : NULL;
     return s;
+}
+
+/* The relaxation sub-update R at one point of component i, as its (1+L) x (1+L) matrix on
+   x = [u; zeta_0 .. zeta_{L-1}]:
+     u'      = (u + dt sum_l beta_l zeta_l) / (1 + dt sum_l beta_l)
+     zeta_l' = c_l zeta_l + (1 - c_l) u'
+   (the damping term beta_l (u - zeta_l) taken at the new velocity, the memory variable
+   advanced exactly for a velocity held at u' over the step). */
+static void relax_matrix(const eo_model *m, int i, int64_t p, double R[5][5]) {
+    const int L = m->nmech;
+    const double dt = m->g.dt;
+    double beta[4], B = 0.0;
+    for (int l = 0; l < L; ++l) {
+        beta[l] = m->mech_w[l] * m->beta_u[i][p];
+        B += beta[l];
+    }
+    const double a = 1.0 / (1.0 + dt * B);
+    R[0][0] = a;
+    for (int l = 0; l < L; ++l) R[0][1 + l] = dt * beta[l] * a;
+    for (int l = 0; l < L; ++l) {
+        R[1 + l][0] = (1.0 - m->mech_c[l]) * R[0][0];
+        for (int k = 0; k < L; ++k) R[1 + l][1 + k] = (1.0 - m->mech_c[l]) * R[0][1 + k] + (l == k ? m->mech_c[l] : 0.0);
+    }
+}
+
+/* x <- R x (transpose = 0) or x <- R^T x (transpose = 1) at every point and component. */
+static void relax(const eo_model *m, eo_view *s, int transpose) {
+    const int L = m->nmech;
+    for (int i = 0; i < 3; ++i) {
+#pragma omp parallel for schedule(static)
+        for (int64_t p = 0; p < m->N; ++p) {
+            double R[5][5], x[5], y[5] = {0.0};
+            relax_matrix(m, i, p, R);
+            x[0] = s->u[i][p];
+            for (int l = 0; l < L; ++l) x[1 + l] = s->zeta[l][i][p];
+            for (int r = 0; r <= L; ++r) {
+                y[r] = 0.0;
+                for (int c = 0; c <= L; ++c) y[r] += (transpose ? R[c][r] : R[r][c]) * x[c];
+            }
+            s->u[i][p] = y[0];
+            for (int l = 0; l < L; ++l) s->zeta[l][i][p] = y[1 + l];
+        }
+    }
 }
 
 /* Derivative type of the velocity update along axis j for u^i (Sec. 2.2):
@@ -222,6 +287,8 @@ static void step_fwd(const eo_model *m, double *v, double *tmp) {
             s.u[i][p] = (1.0 - dt * m->alpha_u[i][p]) * s.u[i][p] + dt / m->rho_u[i][p] * acc;
         }
     }
+    /* (2b) frequency-dependent absorption: the relaxation sub-update R on (u, zeta) */
+    if (m->nmech > 0) relax(m, &s, 0);
     /* (3) psi^{ij}_{m+1} = b_j psi^{ij}_m + a_j D_j u^i_{m+1/2} */
     for (int i = 0; i < 3; ++i)
         for (int j = 0; j < 3; ++j) {
@@ -315,6 +382,8 @@ static void step_tr(const eo_model *m, double *v, double *tmp) {
 #pragma omp parallel for schedule(static)
             for (int64_t p = 0; p < N; ++p) s.psi[i][j][p] *= prof(m, m->pb, j, h, p);
         }
+    /* (2b)^T: the transposed relaxation matrix on (u~, zeta~) */
+    if (m->nmech > 0) relax(m, &s, 1);
     /* (2)^T: u' = J u + Phi sigma + Gamma phi.
        Adjoint: sigma~ += Phi^T u~, phi~ += Gamma^T u~ (with the incoming u~), then u~ <- J u~. */
     for (int i = 0; i < 3; ++i) {
@@ -346,7 +415,7 @@ static void step_tr(const eo_model *m, double *v, double *tmp) {
 
 /* v'_0 = tau' p0 : sigma_kk = -p0/3, everything else zero (Sec. 3, eq. initialp0). */
 static void inject(const eo_model *m, const double *p0, double *v) {
-    memset(v, 0, sizeof(double) * 27 * m->N);
+    memset(v, 0, sizeof(double) * state_len(m));
     eo_view s = view(m, v);
     for (int64_t p = 0; p < m->N; ++p)
         for (int k = 0; k < 3; ++k) s.sig[k][p] = -p0[p] / 3.0;
@@ -519,7 +588,7 @@ eo_model *eo_model_create(const eo_grid *g, const float *lam, const float *mu, c
 
 void eo_model_free(eo_model *m) {
     if (!m) return;
-    for (int i = 0; i < 3; ++i) { free(m->rho_u[i]); free(m->alpha_u[i]); free(m->mu_s[i]); }
+    for (int i = 0; i < 3; ++i) { free(m->rho_u[i]); free(m->alpha_u[i]); free(m->mu_s[i]); free(m->beta_u[i]); }
     free(m->lam); free(m->mu);
     for (int a = 0; a < 3; ++a)
         for (int h = 0; h < 2; ++h) { free(m->pa[a][h]); free(m->pb[a][h]); free(m->pchi[a][h]); }
@@ -558,7 +627,45 @@ void eo_receivers(const eo_model *m, int64_t *base, double *w) {
     memcpy(w, m->rw, sizeof(double) * 8 * m->nrec);
 }
 
-/* In-place v <- W' v or v <- W'^T v on a 27N state. */
+/* Frequency-dependent absorption: nmech (1..4) relaxation mechanisms with angular frequencies
+   omega_l > 0 and weights w_l >= 0, and the cell map alpha_r >= 0 (1/s) of their strength; at a
+   u^i point beta_u is the mean of the two adjacent cells (as alpha, the upper neighbour
+   replicated at the last index) and beta_l = w_l beta_u.  nmech = 0 removes them.  The state
+   grows to (27 + 3 nmech) N (eo_state_len).  Returns 0, or -1 for invalid arguments. */
+int eo_set_relaxation(eo_model *m, int32_t nmech, const double *omega, const double *weight, const float *alpha_r) {
+    if (nmech < 0 || nmech > 4) return -1;
+    for (int i = 0; i < 3; ++i) { free(m->beta_u[i]); m->beta_u[i] = NULL; }
+    m->nmech = 0;
+    if (nmech == 0) return 0;
+    for (int l = 0; l < nmech; ++l)
+        if (!(omega[l] > 0.0) || !(weight[l] >= 0.0) || !isfinite(omega[l]) || !isfinite(weight[l])) return -1;
+    const int64_t N = m->N;
+    for (int64_t p = 0; p < N; ++p)
+        if (!(alpha_r[p] >= 0.0f) || !isfinite(alpha_r[p])) return -1;
+    for (int i = 0; i < 3; ++i) m->beta_u[i] = (double *)malloc(sizeof(double) * N);
+    for (int k = 0; k < m->n[2]; ++k)
+        for (int j = 0; j < m->n[1]; ++j)
+            for (int i = 0; i < m->n[0]; ++i) {
+                const int c[3] = {i, j, k};
+                const int64_t p = i + (int64_t)m->n[0] * (j + (int64_t)m->n[1] * k);
+                for (int a = 0; a < 3; ++a) {
+                    int cc[3] = {c[0], c[1], c[2]};
+                    cc[a] = clampi(c[a] + 1, 0, m->n[a] - 1);
+                    const int64_t q = cc[0] + (int64_t)m->n[0] * (cc[1] + (int64_t)m->n[1] * cc[2]);
+                    m->beta_u[a][p] = 0.5 * ((double)alpha_r[p] + (double)alpha_r[q]);
+                }
+            }
+    for (int l = 0; l < nmech; ++l) {
+        m->mech_w[l] = weight[l];
+        m->mech_c[l] = exp(-omega[l] * m->g.dt);
+    }
+    m->nmech = nmech;
+    return 0;
+}
+
+int64_t eo_state_len(const eo_model *m) { return state_len(m); }
+
+/* In-place v <- W' v or v <- W'^T v on a state of eo_state_len() doubles. */
 void eo_step(const eo_model *m, double *v, int transpose) {
     double *tmp = (double *)malloc(sizeof(double) * 4 * m->N);
     if (transpose) step_tr(m, v, tmp); else step_fwd(m, v, tmp);
@@ -573,7 +680,7 @@ void eo_measure_tr(const eo_model *m, const double *y, double *v) { measure_tr(m
 /* traces[M][L] = H p0  (eq. STforHPML), nsteps_override > 0 replaces M. */
 int eo_forward(const eo_model *m, const double *p0, double *traces, int32_t nsteps_override) {
     const int M = nsteps_override > 0 ? nsteps_override : m->g.nsteps;
-    double *v = (double *)malloc(sizeof(double) * 27 * m->N);
+    double *v = (double *)malloc(sizeof(double) * state_len(m));
     double *tmp = (double *)malloc(sizeof(double) * 4 * m->N);
     if (!v || !tmp) { free(v); free(tmp); return -4; }
     inject(m, p0, v);
@@ -590,7 +697,7 @@ int eo_forward(const eo_model *m, const double *p0, double *traces, int32_t nste
    p_adj = tau'^T v_0   (Sec. 4, eq. Adjup; Appendix eq. AdjupPML with the index read as m-1). */
 int eo_adjoint(const eo_model *m, const double *y, double *p_adj, int32_t nsteps_override) {
     const int M = nsteps_override > 0 ? nsteps_override : m->g.nsteps;
-    double *v = (double *)calloc((size_t)27 * m->N, sizeof(double));
+    double *v = (double *)calloc((size_t)state_len(m), sizeof(double));
     double *tmp = (double *)malloc(sizeof(double) * 4 * m->N);
     if (!v || !tmp) { free(v); free(tmp); return -4; }
     measure_tr(m, y + (int64_t)(M - 1) * m->nrec, v);
@@ -603,7 +710,7 @@ int eo_adjoint(const eo_model *m, const double *y, double *p_adj, int32_t nsteps
     return 0;
 }
 
-/* Run the forward recursion for `steps` updates from v (27N, in/out). */
+/* Run the forward recursion for `steps` updates from v (eo_state_len() doubles, in/out). */
 void eo_run(const eo_model *m, double *v, int32_t steps) {
     double *tmp = (double *)malloc(sizeof(double) * 4 * m->N);
     for (int t = 0; t < steps; ++t) step_fwd(m, v, tmp);

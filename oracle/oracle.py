@@ -71,6 +71,10 @@ def lib():
         L.eo_adjoint.argtypes = [vp, vp, vp, ctypes.c_int32]
         L.eo_run.argtypes = [vp, vp, ctypes.c_int32]
         L.eo_num_threads.restype = ctypes.c_int
+        L.eo_set_relaxation.restype = ctypes.c_int
+        L.eo_set_relaxation.argtypes = [vp, ctypes.c_int32, vp, vp, vp]
+        L.eo_state_len.restype = ctypes.c_int64
+        L.eo_state_len.argtypes = [vp]
         _lib = L
     return _lib
 
@@ -95,7 +99,9 @@ class Model:
     """
 
     def __init__(self, nx, ny, nz, dx, dt, nsteps, npml, lam, mu, rho, alpha, rec,
-                 pml_R=0.0, pml_npower=0.0, pml_f0=0.0):
+                 pml_R=0.0, pml_npower=0.0, pml_f0=0.0, alpha_r=None, mechanisms=None):
+        """alpha_r, mechanisms: frequency-dependent absorption (el_oracle.c, eo_set_relaxation):
+        the cell map of the relaxation strength (1/s) and a list of (omega_l, w_l) pairs."""
         L = lib()
         self.shape = (nz, ny, nx)
         self.nsteps = int(nsteps)
@@ -109,11 +115,23 @@ class Model:
             raise ValueError("oracle: invalid grid, medium or receiver outside the grid")
         self._h = ctypes.c_void_p(h)
         self.N = int(L.eo_ncells(self._h))
+        self.nmech = 0
+        if mechanisms:
+            om = _f64([m[0] for m in mechanisms])
+            wt = _f64([m[1] for m in mechanisms])
+            ar = _f32(alpha_r).reshape(-1)
+            assert ar.size == self.N
+            if L.eo_set_relaxation(self._h, len(mechanisms), _ptr(om), _ptr(wt), _ptr(ar)) != 0:
+                raise ValueError("oracle: invalid relaxation mechanisms or strength map")
+            self.nmech = len(mechanisms)
+        self.state_len = int(L.eo_state_len(self._h))
 
     @classmethod
     def from_scenario(cls, sc, **over):
         kw = dict(nx=sc.nx, ny=sc.ny, nz=sc.nz, dx=sc.dx, dt=sc.dt, nsteps=sc.nsteps,
                   npml=sc.npml, lam=sc.lam, mu=sc.mu, rho=sc.rho, alpha=sc.alpha, rec=sc.rec)
+        if getattr(sc, "mechanisms", None):
+            kw.update(alpha_r=sc.alpha_r, mechanisms=sc.mechanisms)
         kw.update(over)
         return cls(**kw)
 
@@ -144,18 +162,19 @@ class Model:
         return out.reshape(self.shape)
 
     def step(self, v: np.ndarray, transpose: bool = False) -> np.ndarray:
-        """v <- W' v (or W'^T v) in place on a float64 27N state."""
-        assert v.dtype == np.float64 and v.flags.c_contiguous and v.size == 27 * self.N
+        """v <- W' v (or W'^T v) in place on a float64 state of state_len entries (27N, plus
+        3N per relaxation mechanism)."""
+        assert v.dtype == np.float64 and v.flags.c_contiguous and v.size == self.state_len
         lib().eo_step(self._h, _ptr(v), 1 if transpose else 0)
         return v
 
     def run(self, v: np.ndarray, steps: int) -> np.ndarray:
-        assert v.dtype == np.float64 and v.flags.c_contiguous and v.size == 27 * self.N
+        assert v.dtype == np.float64 and v.flags.c_contiguous and v.size == self.state_len
         lib().eo_run(self._h, _ptr(v), int(steps))
         return v
 
     def inject(self, p0) -> np.ndarray:
-        v = np.zeros(27 * self.N)
+        v = np.zeros(self.state_len)
         p = _f64(p0).reshape(-1)
         lib().eo_inject(self._h, _ptr(p), _ptr(v))
         return v
@@ -204,13 +223,15 @@ class Model:
 
     # ------------------------------------------------------------ state views
     def state_views(self, v: np.ndarray) -> dict:
-        """Named views of a 27N state: phi[3][3], u[3], psi[3][3], sig[6] (Voigt order)."""
+        """Named views of a state: phi[3][3], u[3], psi[3][3], sig[6] (Voigt order) and the
+        relaxation memory variables zeta[l][3]."""
         N, sh = self.N, self.shape
         f = lambda k: v[k * N:(k + 1) * N].reshape(sh)
         return dict(phi=[[f(3 * i + j) for j in range(3)] for i in range(3)],
                     u=[f(9 + i) for i in range(3)],
                     psi=[[f(12 + 3 * i + j) for j in range(3)] for i in range(3)],
-                    sig=[f(21 + a) for a in range(6)])
+                    sig=[f(21 + a) for a in range(6)],
+                    zeta=[[f(27 + 3 * l + i) for i in range(3)] for l in range(self.nmech)])
 
 
 def num_threads() -> int:

@@ -51,6 +51,10 @@ class Scenario:
     alpha: np.ndarray    # float32, 1/s
     p0: np.ndarray       # float32, Pa
     rec: np.ndarray      # float64 [L][3], metres from the centre of cell (0,0,0); columns x, y, z
+    # frequency-dependent absorption (optional): strength map alpha_r (float32, 1/s) and the
+    # relaxation mechanisms as (omega_l in rad/s, weight w_l) pairs
+    alpha_r: np.ndarray | None = None
+    mechanisms: list | None = None
 
     @property
     def shape(self):

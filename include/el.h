@@ -64,6 +64,32 @@ typedef int32_t el_status;
 #define EL_F32 0          /* fields, stencils, p0 and p_adj in float  */
 #define EL_F64 1          /* fields, stencils, p0 and p_adj in double */
 
+/*
+ * Frequency-dependent absorption.  The paper's absorption is diffusive: the
+ * velocity is damped at a rate alpha that does not depend on frequency
+ * (Sec. 2.1, eq. subeq1); its conclusion (Sec. 8) names a frequency-dependent
+ * attenuation model as the next step.  With nmech > 0 relaxation mechanisms
+ * join the damping term:
+ *
+ *   d/dt u + alpha u + sum_l beta_l (u - zeta_l) = div(sigma) / rho,
+ *   d/dt zeta_l = omega_l (u - zeta_l),   beta_l = weight[l] * alpha_r,
+ *
+ * i.e. a damping rate a(w) = alpha + sum_l beta_l i w / (omega_l + i w) that
+ * rises with frequency w.  alpha_r is a cell map (el_plan_create), averaged
+ * at the velocity points like alpha.  Discretely, every step's velocity
+ * update is followed by the pointwise sub-update
+ *   u' = (u + dt sum_l beta_l zeta_l) / (1 + dt sum_l beta_l),
+ *   zeta_l' = c_l zeta_l + (1 - c_l) u',   c_l = exp(-omega_l dt),
+ * and the adjoint applies its transpose at the mirrored place, so H^T stays
+ * the exact transpose.  nmech = 0 is the paper's diffusive model.
+ */
+#define EL_MAX_MECH 4
+typedef struct {
+    int32_t nmech;              /* 0 .. EL_MAX_MECH relaxation mechanisms                      */
+    double  omega[EL_MAX_MECH]; /* their angular frequencies omega_l > 0 (rad/s)               */
+    double  weight[EL_MAX_MECH];/* their weights w_l >= 0                                      */
+} el_relaxation;
+
 typedef struct {
     int32_t nx, ny, nz;   /* cells per axis, C-PML included; each >= 4 and >= 2*npml + 2      */
     double  dx;           /* grid spacing (m), the same on every axis                          */
@@ -75,6 +101,7 @@ typedef struct {
     double  pml_f0;       /* frequency (Hz) of the profile's beta = pi f0 (1 - xi);            */
                           /*   <= 0 selects 1500 / (8 dx)                                      */
     int32_t precision;    /* EL_F32 or EL_F64                                                  */
+    el_relaxation relax;  /* frequency-dependent absorption; all zero = none                  */
 } el_grid;
 
 typedef struct el_plan_* el_plan;
@@ -92,8 +119,10 @@ const char *el_last_error(void);
  * Host-only checks of a grid and a receiver set: sizes, spacing, PML
  * thickness, precision, that every array the kernels address (a padded
  * volume, a C-PML memory-variable slab of 2 (npml + 7) planes) stays below
- * 4 GiB, and that every receiver lies in [0, n-1]*dx (up to
- * 1e-9 cells of rounding; such receivers are clamped onto the box).
+ * 4 GiB, the relaxation mechanisms (nmech in 0..EL_MAX_MECH, every omega_l
+ * > 0 and weight w_l >= 0 finite), and that every receiver lies in
+ * [0, n-1]*dx (up to 1e-9 cells of rounding; such receivers are clamped
+ * onto the box).
  * rec_xyz (host): nrec x 3 doubles, metres from the centre of cell (0,0,0),
  * columns x, y, z.  nrec may be 0 (rec_xyz may then be NULL).
  * Returns EL_EINVAL or EL_ERANGE on failure.  Touches no device.
@@ -117,6 +146,12 @@ el_status el_plan_bytes(const el_grid *grid, int32_t nrec, size_t *bytes);
  *       Sec. 2.1), 0 <= dt*alpha < 1, all finite (EL_EINVAL /
  *       EL_EUNSTABLE), and max sqrt((lambda+2mu)/rho) dt/dx <= 6/(7 sqrt 3)
  *       (EL_EUNSTABLE).  They may be freed once this call returns.
+ *   alpha_r (device): with grid->relax.nmech > 0, N floats, the strength of
+ *       the relaxation mechanisms in 1/s (see el_relaxation); finite, >= 0,
+ *       and 0 on every cell within npml + 2 cells of a face (the C-PML
+ *       layers and their neighbours: the adjoint's layer variables are
+ *       updated inside the velocity pass, before the transposed relaxation),
+ *       else EL_EINVAL.  Ignored (may be NULL) when nmech = 0.
  *   rec_xyz (host): nrec x 3 doubles as in el_grid_check().
  *   workspace (device): at least el_plan_bytes() bytes, 256-byte aligned,
  *       owned by the caller, valid until el_plan_destroy().
@@ -125,7 +160,7 @@ el_status el_plan_bytes(const el_grid *grid, int32_t nrec, size_t *bytes);
  */
 el_status el_plan_create(el_plan *out, const el_grid *grid,
                          const float *lambda, const float *mu, const float *rho, const float *alpha,
-                         const double *rec_xyz, int32_t nrec,
+                         const float *alpha_r, const double *rec_xyz, int32_t nrec,
                          void *workspace, size_t workspace_bytes, void *stream);
 
 /* Release the plan's host state.  The workspace stays the caller's. */
@@ -158,8 +193,9 @@ el_status el_forward(el_plan plan, const void *p0, double *traces, void *stream)
  *   energy (device): ceil((nsteps - 1) / every) doubles (none when
  *       nsteps = 1; energy may then be NULL), fully overwritten in order of m.
  * Deterministic (fixed reduction order).  Asynchronous on `stream`.
- * Errors: EL_EINVAL for a NULL plan, p0, traces (nrec > 0) or energy, or
- * every < 1.
+ * Errors: EL_EINVAL for a NULL plan, p0, traces (nrec > 0) or energy,
+ * every < 1, or a plan with relaxation mechanisms (their memory variables
+ * hold energy this sum does not count).
  */
 el_status el_forward_energy(el_plan plan, const void *p0, double *traces, int32_t every, double *energy,
                             void *stream);
@@ -305,7 +341,9 @@ el_status el_plan_fluid_path(el_plan plan, int32_t enable, el_fluid_stats *stats
 #define EL_K_ADJ_STRESS   3   /* adjoint pass producing the stress adjoint     */
 #define EL_K_GATHER       4   /* receiver gather of the last trace row         */
 #define EL_K_SCATTER      5   /* receiver scatter (adjoint)                    */
-#define EL_K_COUNT        6
+#define EL_K_RELAX        6   /* relaxation sub-update (forward) or its        */
+                              /* transpose (adjoint), plans with nmech > 0     */
+#define EL_K_COUNT        7
 
 /*
  * Benchmark instrumentation.  With every = n >= 1, the kernel launches of the

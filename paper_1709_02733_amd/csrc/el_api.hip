@@ -103,6 +103,10 @@ bool layout(const el_grid &g, int nrec, Layout *L) {
         L->tile_media = take((size_t)4 * t.ntiles * es);
         L->tile_lanes = take((size_t)2 * kTileY * t.ntiles * 8);
         L->energy = take((size_t)(kTileX * kTileY + 2) * 8 * t.per * sizeof(double));
+        const int nm = g.relax.nmech;
+        L->relax_map = nm > 0 ? take(N * es) : 0;
+        L->relax_flag = nm > 0 ? take((size_t)t.ntiles) : 0;
+        L->relax_zeta = nm > 0 ? take((size_t)t.ntiles * 3 * nm * t.zc * kTileX * kTileY * es) : 0;
     }
     L->partial = take(kStats * kDotBlocks * 8);
     L->total = off;
@@ -229,6 +233,14 @@ el_status el_grid_check(const el_grid *g, const double *rec, int32_t nrec) {
         if (tiles > kTileMask)
             return fail(EL_EINVAL, "grid %dx%dx%d: %lld stencil tiles, at most %d", g->nx, g->ny, g->nz, tiles, kTileMask);
     }
+    {
+        const el_relaxation &rx = g->relax;
+        if (rx.nmech < 0 || rx.nmech > EL_MAX_MECH)
+            return fail(EL_EINVAL, "relax.nmech = %d outside 0..%d", rx.nmech, EL_MAX_MECH);
+        for (int l = 0; l < rx.nmech; ++l)
+            if (!(rx.omega[l] > 0) || !std::isfinite(rx.omega[l]) || !(rx.weight[l] >= 0) || !std::isfinite(rx.weight[l]))
+                return fail(EL_EINVAL, "relaxation mechanism %d: omega must be > 0 and weight >= 0, both finite", l);
+    }
     if (nrec < 0) return fail(EL_EINVAL, "nrec must be >= 0");
     if (nrec > (1 << 26)) return fail(EL_EINVAL, "too many receivers");
     if (nrec > 0 && !rec) return fail(EL_EINVAL, "rec_xyz is NULL");
@@ -314,6 +326,23 @@ void bind(Dev<T> &d, el_plan_ *p) {
             d.pb[a][h] = g.npml > 0 ? reinterpret_cast<T *>(ws + p->L.pb[a][h]) : nullptr;
         }
         for (int q = 0; q < 6; ++q) d.mem[a][q] = g.npml > 0 ? reinterpret_cast<T *>(ws + p->L.mem[a][q]) : nullptr;
+    }
+}
+
+// Relaxation parameters in the plan's precision: weights, c_l = exp(-omega_l dt), buffers.
+template <typename T>
+void bind_relax(Relax<T> &r, el_plan_ *p) {
+    const el_relaxation &rx = p->g.relax;
+    r = Relax<T>{};
+    r.L = rx.nmech;
+    for (int l = 0; l < rx.nmech; ++l) {
+        r.w[l] = T(rx.weight[l]);
+        r.c[l] = T(std::exp(-rx.omega[l] * p->g.dt));
+    }
+    if (rx.nmech > 0) {
+        r.ar = reinterpret_cast<T *>(p->ws + p->L.relax_map);
+        r.zeta = reinterpret_cast<T *>(p->ws + p->L.relax_zeta);
+        r.flag = reinterpret_cast<unsigned char *>(p->ws + p->L.relax_flag);
     }
 }
 
@@ -472,7 +501,9 @@ el_status run_forward(el_plan p, Dev<T> &d, const T *p0, double *traces, hipStre
     double *ekin = reinterpret_cast<double *>(p->ws + p->L.energy);   // per thread
     double *ekb = ekin + (size_t)nb * kTileX * kTileY;                 // per block
     double *epot = ekb + nb;
+    const Relax<T> &rx = plan_relax<T>(p);
     HIP_TRY(launch_zero_state(d, s), "zero state");
+    HIP_TRY(launch_relax_zero(p->tiles, rx, s), "relaxation state");
     HIP_TRY(launch_inject(d, p0, s), "inject");
     // trace row m-1 is gathered by extra blocks of velocity pass m (which reads those stresses
     // and writes none); the last row by a gather launch of its own
@@ -484,6 +515,8 @@ el_status run_forward(el_plan p, Dev<T> &d, const T *p0, double *traces, hipStre
                       [&] { return launch_velocity(d, p->tiles, s, &p->rec, row, en ? ekin : nullptr); }),
                 "velocity pass");
         if (en) HIP_TRY(launch_energy_final(ekin, ekb, epot, nb, energy + (m - 1) / every, s), "energy");
+        if (rx.L > 0)
+            HIP_TRY(timed(p, EL_K_RELAX, m, s, [&] { return launch_relax(d, p->tiles, rx, false, s); }), "relaxation");
         HIP_TRY(timed(p, EL_K_STRESS, m, s, [&] { return launch_stress(d, p->tiles, s); }), "stress pass");
     }
     HIP_TRY(timed(p, EL_K_GATHER, M - 1, s, [&] { return launch_gather(d, p->rec, traces + (size_t)(M - 1) * L, s); }),
@@ -495,12 +528,18 @@ el_status run_forward(el_plan p, Dev<T> &d, const T *p0, double *traces, hipStre
 template <typename T>
 el_status run_adjoint(el_plan p, Dev<T> &d, const double *y, T *out, hipStream_t s) {
     const int M = p->g.nsteps, L = p->nrec;
+    const Relax<T> &rx = plan_relax<T>(p);
     HIP_TRY(launch_zero_state(d, s), "zero state");
+    HIP_TRY(launch_relax_zero(p->tiles, rx, s), "relaxation state");
     HIP_TRY(timed(p, EL_K_SCATTER, M - 1, s, [&] { return launch_scatter(d, p->rec, y + (size_t)(M - 1) * L, s); }),
             "scatter");
     for (int m = M - 1; m >= 1; --m) {
         HIP_TRY(timed(p, EL_K_ADJ_VELOCITY, m, s, [&] { return launch_adj_velocity(d, p->tiles, s); }),
                 "adjoint velocity pass");
+        // the transposed relaxation sits between the transposed stress and velocity updates of
+        // the step (the forward applies R between its velocity and stress updates)
+        if (rx.L > 0)
+            HIP_TRY(timed(p, EL_K_RELAX, m, s, [&] { return launch_relax(d, p->tiles, rx, true, s); }), "relaxation");
         HIP_TRY(timed(p, EL_K_ADJ_STRESS, m, s, [&] { return launch_adj_stress(d, p->tiles, s); }), "adjoint stress pass");
         HIP_TRY(timed(p, EL_K_SCATTER, m - 1, s, [&] { return launch_scatter(d, p->rec, y + (size_t)(m - 1) * L, s); }),
                 "scatter");
@@ -515,13 +554,14 @@ el_status run_adjoint(el_plan p, Dev<T> &d, const double *y, T *out, hipStream_t
 extern "C" {
 
 el_status el_plan_create(el_plan *out, const el_grid *grid, const float *lam, const float *mu, const float *rho,
-                         const float *alpha, const double *rec, int32_t nrec, void *workspace,
+                         const float *alpha, const float *alpha_r, const double *rec, int32_t nrec, void *workspace,
                          size_t workspace_bytes, void *stream) {
     if (!out) return fail(EL_EINVAL, "out is NULL");
     *out = nullptr;
     el_status st = el_grid_check(grid, rec, nrec);
     if (st != EL_OK) return st;
     if (!lam || !mu || !rho || !alpha) return fail(EL_EINVAL, "a material map is NULL");
+    if (grid->relax.nmech > 0 && !alpha_r) return fail(EL_EINVAL, "alpha_r is NULL with relaxation mechanisms");
     if (!workspace) return fail(EL_EINVAL, "workspace is NULL");
     if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0) return fail(EL_EINVAL, "workspace is not 256-byte aligned");
     Layout L;
@@ -567,21 +607,46 @@ el_status el_plan_create(el_plan *out, const el_grid *grid, const float *lam, co
     const double cfl = p->cmax * grid->dt / grid->dx;
     if (cfl > kCflMax)
         return bail(fail(EL_EUNSTABLE, "CFL c_max dt/dx = %.6g exceeds the 4th-order staggered limit %.6g", cfl, kCflMax));
+    if (grid->relax.nmech > 0) {
+        // alpha_r: finite, >= 0, and zero within npml + 2 cells of a face
+        const int margin = grid->npml > 0 ? grid->npml + 2 : 0;
+        e = launch_relax_stats(alpha_r, grid->nx, grid->ny, grid->nz, margin, stats + 8, partial, s);
+        double rs[3] = {0, 0, 0};
+        if (e == hipSuccess) e = hipMemcpyAsync(rs, stats + 8, sizeof rs, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return bail(hip_fail(e, "relaxation strength statistics"));
+        if (rs[1] > 0) return bail(fail(EL_EINVAL, "%.0f non-finite alpha_r values", rs[1]));
+        if (rs[0] < 0) return bail(fail(EL_EINVAL, "alpha_r must be >= 0 (min %.6g)", rs[0]));
+        if (rs[2] > 0)
+            return bail(fail(EL_EINVAL, "alpha_r must be 0 within npml + 2 = %d cells of a face (max there %.6g)",
+                             margin, rs[2]));
+    }
 
     e = hipEventCreateWithFlags(&p->done, hipEventDisableTiming);
     if (e != hipSuccess) return bail(hip_fail(e, "event"));
     if (grid->precision == EL_F64) {
         bind(p->dd, p);
+        bind_relax(p->rd, p);
         e = launch_convert_maps(p->dd, lam, mu, rho, alpha, s);
+        if (e == hipSuccess && p->rd.L > 0) e = launch_relax_setup(p->dd, p->tiles, alpha_r, p->rd, s);
         if (e != hipSuccess) return bail(hip_fail(e, "copy maps"));
         st = upload_pml(p, p->dd, s);
     } else {
         bind(p->df, p);
+        bind_relax(p->rf, p);
         e = launch_convert_maps(p->df, lam, mu, rho, alpha, s);
+        if (e == hipSuccess && p->rf.L > 0) e = launch_relax_setup(p->df, p->tiles, alpha_r, p->rf, s);
         if (e != hipSuccess) return bail(hip_fail(e, "copy maps"));
         st = upload_pml(p, p->df, s);
     }
     if (st != EL_OK) return bail(st);
+    if (grid->relax.nmech > 0 && p->tiles.ntiles > 0) {
+        std::vector<unsigned char> rflag(p->tiles.ntiles, 0);
+        e = hipMemcpyAsync(rflag.data(), p->ws + L.relax_flag, rflag.size(), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return bail(hip_fail(e, "relaxation tiles"));
+        for (unsigned char f : rflag) p->relax_tiles += f;
+    }
     st = upload_receivers(p, rec, s);
     if (st != EL_OK) return bail(st);
     {
@@ -718,6 +783,9 @@ el_status el_forward_energy(el_plan p, const void *p0, double *traces, int32_t e
     if (!p0 || (!traces && p->nrec > 0)) return fail(EL_EINVAL, "p0 or traces is NULL");
     if (every < 1) return fail(EL_EINVAL, "every must be >= 1");
     if (!energy && p->g.nsteps > 1) return fail(EL_EINVAL, "energy is NULL");
+    if (p->g.relax.nmech > 0)
+        return fail(EL_EINVAL, "the modified energy is not defined with relaxation mechanisms (their memory variables "
+                               "hold energy it does not count)");
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     HIP_TRY(hipStreamWaitEvent(s, p->done, 0), "order after the previous operation");
     st = p->g.precision == EL_F64

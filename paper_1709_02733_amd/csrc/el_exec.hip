@@ -49,12 +49,15 @@ el_status hipf(hipError_t e, const char *what) {
 template <typename T>
 hipError_t launch_step(el_plan p, const Dev<T> &d, int op, void *traces, int *ctr, hipStream_t s) {
     hipError_t e;
+    const Relax<T> &rx = plan_relax<T>(p);
     if (op == EL_OP_FORWARD) {
         e = launch_velocity(d, p->tiles, s);
+        if (e == hipSuccess) e = launch_relax(d, p->tiles, rx, false, s);
         if (e == hipSuccess) e = launch_stress(d, p->tiles, s);
         if (e == hipSuccess) e = launch_gather_ctr(d, p->rec, static_cast<double *>(traces), ctr, s);
     } else {
         e = launch_adj_velocity(d, p->tiles, s);
+        if (e == hipSuccess) e = launch_relax(d, p->tiles, rx, true, s);
         if (e == hipSuccess) e = launch_adj_stress(d, p->tiles, s);
         if (e == hipSuccess) e = launch_scatter_ctr(d, p->rec, static_cast<const double *>(traces), ctr, s);
     }
@@ -91,6 +94,7 @@ el_status start_op(el_exec ex, ExecSlot &sl, el_plan p, const Dev<T> &d, int op,
     EX_TRY(hipStreamWaitEvent(s, sl.ready, 0), "order after the caller's stream");
     EX_TRY(hipStreamWaitEvent(s, p->done, 0), "order after the plan's previous operation");
     EX_TRY(launch_zero_state(d, s), "zero state");
+    EX_TRY(launch_relax_zero(p->tiles, plan_relax<T>(p), s), "relaxation state");
     if (op == EL_OP_FORWARD) {
         EX_TRY(launch_inject(d, static_cast<const T *>(in), s), "inject");
         EX_TRY(launch_gather(d, p->rec, static_cast<double *>(out), s), "gather");

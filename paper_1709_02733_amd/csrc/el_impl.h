@@ -143,6 +143,20 @@ std::vector<int> tile_order(const Tiles &t, const unsigned char *fast, const uns
 // Bits kEdgeShift.. of tile q's entry (0 unless q is a fluid tile).
 int tile_edges(const Tiles &t, const unsigned char *fast, int q);
 
+// Relaxation mechanisms of the frequency-dependent absorption (el_relaxation): after every
+// velocity pass the tiles holding a velocity point with beta > 0 apply the pointwise
+// sub-update R (forward) or R^T (adjoint) to u and the memory variables zeta_l.
+template <typename T>
+struct Relax {
+    int L;                   // mechanisms (0: none)
+    T w[EL_MAX_MECH];        // weights
+    T c[EL_MAX_MECH];        // exp(-omega_l dt)
+    const T *ar;             // strength alpha_r, a padded cell map (edge-replicated like the others)
+    T *zeta;                 // [tile][l][component][plane of the chunk][row][column]: kTileX * kTileY
+                             // * zc values per (tile, l, component)
+    const unsigned char *flag;   // per tile: 1 if some velocity point of it has beta > 0
+};
+
 // Receiver tables (cell offsets are padded element indices).
 struct Rec {
     int nrec;
@@ -200,6 +214,9 @@ struct Layout {
     size_t partial;          // reduction partials
     size_t energy;           // modified energy: kinetic part of each thread of the tile blocks, then
                              // kinetic and potential part of each tile block
+    size_t relax_map;        // alpha_r (padded cell map), with relaxation mechanisms only
+    size_t relax_flag;       // per tile: relaxation applies
+    size_t relax_zeta;       // memory variables of the relaxation mechanisms (Relax::zeta)
     size_t total;
 };
 
@@ -242,6 +259,16 @@ hipError_t launch_eir(const double *h, int nh, const double *in, double *out, in
 template <typename T> hipError_t launch_dot(const T *a, const T *b, long long n, double *partial, double *out,
                                             hipStream_t s);
 hipError_t launch_set_counter(int *ctr, int v, hipStream_t s);
+// Relaxation: statistics of the strength map (stats[0] min, [1] non-finite count, [2] max
+// over the cells within `margin` of a face), its padded copy, the per-tile flags, the
+// memory variables' reset, and the pointwise sub-update (ADJ: its transpose).
+hipError_t launch_relax_stats(const float *ar, int nx, int ny, int nz, int margin, double *stats, double *partial,
+                              hipStream_t s);
+template <typename T> hipError_t launch_relax_setup(const Dev<T> &d, const Tiles &tl, const float *ar_cells,
+                                                    const Relax<T> &r, hipStream_t s);
+template <typename T> hipError_t launch_relax_zero(const Tiles &tl, const Relax<T> &r, hipStream_t s);
+template <typename T> hipError_t launch_relax(const Dev<T> &d, const Tiles &tl, const Relax<T> &r, bool adjoint,
+                                              hipStream_t s);
 template <typename T> hipError_t launch_gather_ctr(const Dev<T> &d, const Rec &r, double *traces, int *ctr,
                                                    hipStream_t s);
 template <typename T> hipError_t launch_scatter_ctr(const Dev<T> &d, const Rec &r, const double *traces, int *ctr,
@@ -259,6 +286,9 @@ struct el_plan_ {
     int device;
     el::Dev<float> df;
     el::Dev<double> dd;
+    el::Relax<float> rf;               // relaxation mechanisms (L = 0: none)
+    el::Relax<double> rd;
+    long long relax_tiles = 0;         // tiles the relaxation sub-update visits
     el::Rec rec;
     el::Tiles tiles;
     std::vector<unsigned char> fast;   // per tile: the fluid update applies (host copy)
@@ -278,3 +308,8 @@ struct el_plan_ {
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[EL_K_COUNT];
     size_t used[EL_K_COUNT] = {};
 };
+
+// The plan's relaxation parameters in the plan's precision.
+template <typename T> inline el::Relax<T> &plan_relax(el_plan_ *p);
+template <> inline el::Relax<float> &plan_relax<float>(el_plan_ *p) { return p->rf; }
+template <> inline el::Relax<double> &plan_relax<double>(el_plan_ *p) { return p->rd; }

@@ -467,6 +467,188 @@ hipError_t launch_eir(const double *h, int nh, const double *in, double *out, in
     return hipGetLastError();
 }
 
+// ------------------------------------------------- frequency-dependent absorption
+//
+// Relaxation mechanisms l (include/el.h, el_relaxation): after each velocity pass,
+//   u' = (u + dt sum_l beta_l zeta_l) / (1 + dt B),  zeta_l' = c_l zeta_l + (1 - c_l) u'
+// with beta_l = w_l beta, B = sum_l beta_l, beta the mean of alpha_r over the two cells
+// adjacent to the velocity point; the adjoint applies the transposed matrix,
+//   s = r + sum_l (1 - c_l) z_l,  r' = s / (1 + dt B),  z_l' = dt beta_l s / (1 + dt B) + c_l z_l.
+// Both are pointwise, so the adjoint's scaled variable r = q / rho takes the transpose as is.
+// Where beta = 0 the forward leaves u alone and the adjoint's z stays zero, so only tiles
+// holding a velocity point with beta > 0 are visited (flag).
+
+// [0] min alpha_r, [1] non-finite count, [2] max alpha_r over the cells within `margin` of a face.
+__global__ void k_relax_stats_partial(const float *ar, int nx, int ny, int nz, int margin, double *partial) {
+    double v[3] = {INFINITY, 0.0, 0.0};
+    const long long n = (long long)nx * ny * nz;
+    for (long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x; p < n; p += (long long)gridDim.x * blockDim.x) {
+        const double a = ar[p];
+        if (!isfinite(a)) v[1] += 1.0;
+        v[0] = fmin(v[0], a);
+        const long long nxy = (long long)nx * ny;
+        const int k = (int)(p / nxy), j = (int)((p - (long long)k * nxy) / nx), i = (int)(p % nx);
+        if (i < margin || j < margin || k < margin || i >= nx - margin || j >= ny - margin || k >= nz - margin)
+            v[2] = fmax(v[2], fabs(a));
+    }
+    __shared__ double sh[3][256];
+    for (int q = 0; q < 3; ++q) sh[q][threadIdx.x] = v[q];
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) {
+            const int t = threadIdx.x;
+            sh[0][t] = fmin(sh[0][t], sh[0][t + st]);
+            sh[1][t] = sh[1][t] + sh[1][t + st];
+            sh[2][t] = fmax(sh[2][t], sh[2][t + st]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        for (int q = 0; q < 3; ++q) partial[q * kDotBlocks + blockIdx.x] = sh[q][0];
+}
+
+__global__ void k_relax_stats_final(const double *partial, int nb, double *stats) {
+    if (threadIdx.x != 0) return;
+    double v[3] = {INFINITY, 0.0, 0.0};
+    for (int b = 0; b < nb; ++b) {
+        v[0] = fmin(v[0], partial[b]);
+        v[1] += partial[kDotBlocks + b];
+        v[2] = fmax(v[2], partial[2 * kDotBlocks + b]);
+    }
+    for (int q = 0; q < 3; ++q) stats[q] = v[q];
+}
+
+hipError_t launch_relax_stats(const float *ar, int nx, int ny, int nz, int margin, double *stats, double *partial,
+                              hipStream_t s) {
+    const int nb = 128;
+    hipLaunchKernelGGL(k_relax_stats_partial, dim3(nb), dim3(256), 0, s, ar, nx, ny, nz, margin, partial);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_relax_stats_final, dim3(1), dim3(64), 0, s, partial, nb, stats);
+    return hipGetLastError();
+}
+
+// Padded copy of alpha_r (as k_convert_maps: the +x, +y, +z padding holds the nearest cell).
+template <typename T>
+__global__ void k_relax_map(Dev<T> d, const float *ar, T *dst, long long total) {
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total; e += (long long)gridDim.x * blockDim.x) {
+        const long long zp = e / d.plane;
+        const long long rem = e - zp * d.plane;
+        const int y = (int)(rem / d.px), x = (int)(rem - (long long)y * d.px);
+        const int z = (int)zp - 2;
+        T v = T(0);
+        if (z >= 0 && z <= d.nz && y <= d.ny && x <= d.nx)
+            v = T(ar[min(x, d.nx - 1) + (long long)d.nx * (min(y, d.ny - 1) + (long long)d.ny * min(z, d.nz - 1))]);
+        dst[e] = v;
+    }
+}
+
+// Tile q is flagged when alpha_r > 0 on one of its cells or on their +x, +y, +z neighbours
+// (the cells whose means give beta at the tile's velocity points).
+template <typename T>
+__global__ __launch_bounds__(256) void k_relax_flags(Dev<T> d, Tiles tl, const T *ar, unsigned char *flag) {
+    const int q = blockIdx.x;
+    if (q >= tl.ntiles) return;
+    const int bx = q % tl.ntx, r = q / tl.ntx, by = r % tl.nty, bz = r / tl.nty;
+    const int x0 = bx * kTileX, y0 = by * kTileY, z0 = bz * tl.zc;
+    const int w = min(kTileX, d.nx - x0) + 1, hgt = min(kTileY, d.ny - y0) + 1, dep = min(tl.zc, d.nz - z0) + 1;
+    int any = 0;
+    for (long long e = threadIdx.x; e < (long long)w * hgt * dep; e += blockDim.x) {
+        const int xx = x0 + (int)(e % w);
+        const long long rr = e / w;
+        const int yy = y0 + (int)(rr % hgt), zz = z0 + (int)(rr / hgt);
+        if (ar[(long long)(zz + 2) * d.plane + (long long)yy * d.px + xx] > T(0)) any = 1;
+    }
+    any = __syncthreads_or(any);
+    if (threadIdx.x == 0) flag[q] = any ? 1 : 0;
+}
+
+template <typename T>
+hipError_t launch_relax_setup(const Dev<T> &d, const Tiles &tl, const float *ar_cells, const Relax<T> &r,
+                              hipStream_t s) {
+    const long long total = d.plane * (d.nz + 4);
+    hipLaunchKernelGGL(k_relax_map<T>, dim3(4096), dim3(256), 0, s, d, ar_cells, const_cast<T *>(r.ar), total);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || tl.ntiles == 0) return e;
+    hipLaunchKernelGGL(k_relax_flags<T>, dim3(tl.ntiles), dim3(256), 0, s, d, tl, r.ar,
+                       const_cast<unsigned char *>(r.flag));
+    return hipGetLastError();
+}
+
+// Memory variables of the flagged tiles set to zero (initial state of an operation).
+template <typename T>
+__global__ __launch_bounds__(256) void k_relax_zero(Tiles tl, Relax<T> r) {
+    const int q = blockIdx.x;
+    if (q >= tl.ntiles || !r.flag[q]) return;
+    const long long per = (long long)3 * r.L * tl.zc * kTileX * kTileY;
+    T *z = r.zeta + (long long)q * per;
+    for (long long e = threadIdx.x; e < per; e += blockDim.x) z[e] = T(0);
+}
+
+template <typename T>
+hipError_t launch_relax_zero(const Tiles &tl, const Relax<T> &r, hipStream_t s) {
+    if (r.L == 0 || tl.ntiles == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_relax_zero<T>, dim3(tl.ntiles), dim3(256), 0, s, tl, r);
+    return hipGetLastError();
+}
+
+// The sub-update R (ADJ: R^T) on the tile of each block of the stencil grid (same order table).
+template <typename T, bool ADJ>
+__global__ __launch_bounds__(256) void k_relax(Dev<T> d, Tiles tl, Relax<T> r) {
+    const int ent = tl.order[blockIdx.x];
+    if (ent < 0) return;
+    const int q = ent & kTileMask;
+    if (!r.flag[q]) return;
+    const int bx = q % tl.ntx, rr = q / tl.ntx, by = rr % tl.nty, bz = rr / tl.nty;
+    const int col = (int)threadIdx.x % kTileX, row = (int)threadIdx.x / kTileX;
+    const int i = bx * kTileX + col, j = by * kTileY + row, z0 = bz * tl.zc;
+    if (i >= d.nx || j >= d.ny) return;
+    const int z1 = min(z0 + tl.zc, d.nz);
+    const long long stride[3] = {1, d.px, d.plane};
+    const long long per_c = (long long)tl.zc * kTileX * kTileY;       // one (l, component) of a tile
+    T *zt = r.zeta + (long long)q * 3 * r.L * per_c + (long long)row * kTileX + col;
+    const T dt = d.dt;
+    for (int k = z0; k < z1; ++k) {
+        const long long e = (long long)(k + 2) * d.plane + (long long)j * d.px + i;
+        const long long zk = (long long)(k - z0) * kTileX * kTileY;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const T beta = T(0.5) * (r.ar[e] + r.ar[e + stride[c]]);
+            if (!(beta > T(0))) continue;          // R is the identity here (and R^T, with z = 0)
+            T bl[EL_MAX_MECH], zl[EL_MAX_MECH];
+            T B = T(0);
+            for (int l = 0; l < r.L; ++l) {
+                bl[l] = r.w[l] * beta;
+                B += bl[l];
+                zl[l] = zt[((long long)l * 3 + c) * per_c + zk];
+            }
+            const T a = T(1) / (T(1) + dt * B);
+            T *u = d.f[U1 + c] + e;
+            if (!ADJ) {
+                T acc = *u;
+                for (int l = 0; l < r.L; ++l) acc += dt * bl[l] * zl[l];
+                const T un = acc * a;
+                *u = un;
+                for (int l = 0; l < r.L; ++l)
+                    zt[((long long)l * 3 + c) * per_c + zk] = r.c[l] * zl[l] + (T(1) - r.c[l]) * un;
+            } else {
+                T sum = *u;
+                for (int l = 0; l < r.L; ++l) sum += (T(1) - r.c[l]) * zl[l];
+                *u = a * sum;
+                for (int l = 0; l < r.L; ++l) zt[((long long)l * 3 + c) * per_c + zk] = dt * bl[l] * a * sum + r.c[l] * zl[l];
+            }
+        }
+    }
+}
+
+template <typename T>
+hipError_t launch_relax(const Dev<T> &d, const Tiles &tl, const Relax<T> &r, bool adjoint, hipStream_t s) {
+    if (r.L == 0) return hipSuccess;
+    if (adjoint) hipLaunchKernelGGL((k_relax<T, true>), dim3(8 * tl.per), dim3(256), 0, s, d, tl, r);
+    else hipLaunchKernelGGL((k_relax<T, false>), dim3(8 * tl.per), dim3(256), 0, s, d, tl, r);
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------ inner products
 
 template <typename T>
@@ -520,7 +702,11 @@ hipError_t launch_dot(const T *a, const T *b, long long n, double *partial, doub
     template hipError_t launch_extract<T>(const Dev<T> &, T *, hipStream_t);                                         \
     template hipError_t launch_gather_ctr<T>(const Dev<T> &, const Rec &, double *, int *, hipStream_t);             \
     template hipError_t launch_scatter_ctr<T>(const Dev<T> &, const Rec &, const double *, int *, hipStream_t);                                         \
-    template hipError_t launch_dot<T>(const T *, const T *, long long, double *, double *, hipStream_t);
+    template hipError_t launch_dot<T>(const T *, const T *, long long, double *, double *, hipStream_t);           \
+    template hipError_t launch_relax_setup<T>(const Dev<T> &, const Tiles &, const float *, const Relax<T> &,      \
+                                              hipStream_t);                                                        \
+    template hipError_t launch_relax_zero<T>(const Tiles &, const Relax<T> &, hipStream_t);                         \
+    template hipError_t launch_relax<T>(const Dev<T> &, const Tiles &, const Relax<T> &, bool, hipStream_t);
 
 EL_INST(float)
 EL_INST(double)

@@ -28,12 +28,21 @@ class ElError(RuntimeError):
         self.status = status
 
 
+MAX_MECH = 4
+
+
+class Relaxation(ctypes.Structure):
+    """el_relaxation (include/el.h): frequency-dependent absorption mechanisms."""
+    _fields_ = [("nmech", ctypes.c_int32), ("omega", ctypes.c_double * MAX_MECH),
+                ("weight", ctypes.c_double * MAX_MECH)]
+
+
 class Grid(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
                 ("dx", ctypes.c_double), ("dt", ctypes.c_double),
                 ("nsteps", ctypes.c_int32), ("npml", ctypes.c_int32),
                 ("pml_R", ctypes.c_double), ("pml_npower", ctypes.c_double), ("pml_f0", ctypes.c_double),
-                ("precision", ctypes.c_int32)]
+                ("precision", ctypes.c_int32), ("relax", Relaxation)]
 
 
 class FluidStats(ctypes.Structure):
@@ -50,7 +59,7 @@ EXPORTS = ("el_version", "el_status_string", "el_last_error", "el_grid_check", "
            "el_plan_field", "el_plan_layout", "el_plan_sizes", "el_plan_fluid_path", "el_plan_timing",
            "el_plan_kernel_time",
            "el_exec_create", "el_exec_destroy", "el_exec_start", "el_exec_poll", "el_exec_wait", "el_exec_slots")
-KERNELS = ("velocity", "stress", "adj_velocity", "adj_stress", "gather", "scatter")
+KERNELS = ("velocity", "stress", "adj_velocity", "adj_stress", "gather", "scatter", "relax")
 
 
 def lib():
@@ -70,7 +79,7 @@ def lib():
         L.el_plan_bytes.restype = st
         L.el_plan_bytes.argtypes = [ctypes.POINTER(Grid), i32, ctypes.POINTER(ctypes.c_size_t)]
         L.el_plan_create.restype = st
-        L.el_plan_create.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(Grid), vp, vp, vp, vp, vp, i32,
+        L.el_plan_create.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(Grid), vp, vp, vp, vp, vp, vp, i32,
                                      vp, ctypes.c_size_t, vp]
         L.el_plan_destroy.restype = st
         L.el_plan_destroy.argtypes = [vp]
@@ -131,10 +140,18 @@ def version() -> str:
     return lib().el_version().decode()
 
 
-def make_grid(nx, ny, nz, dx, dt, nsteps, npml, precision="f32", pml_R=0.0, pml_npower=0.0, pml_f0=0.0) -> Grid:
+def make_grid(nx, ny, nz, dx, dt, nsteps, npml, precision="f32", pml_R=0.0, pml_npower=0.0, pml_f0=0.0,
+              mechanisms=None) -> Grid:
+    """mechanisms: relaxation mechanisms of the frequency-dependent absorption as a list of
+    (omega_l in rad/s, weight w_l) pairs (el_relaxation), None for the diffusive model."""
     prec = {"f32": EL_F32, "f64": EL_F64}[precision] if isinstance(precision, str) else int(precision)
+    rx = Relaxation()
+    mech = list(mechanisms or [])
+    rx.nmech = len(mech)
+    for l, (om, w) in enumerate(mech[:MAX_MECH]):
+        rx.omega[l], rx.weight[l] = float(om), float(w)
     return Grid(int(nx), int(ny), int(nz), float(dx), float(dt), int(nsteps), int(npml),
-                float(pml_R), float(pml_npower), float(pml_f0), prec)
+                float(pml_R), float(pml_npower), float(pml_f0), prec, rx)
 
 
 def grid_check(grid: Grid, rec=None) -> None:
@@ -169,10 +186,15 @@ class Plan:
     """
 
     def __init__(self, nx, ny, nz, dx, dt, nsteps, npml, lam, mu, rho, alpha, rec,
-                 precision="f32", pml_R=0.0, pml_npower=0.0, pml_f0=0.0, device=None, stream=None):
+                 precision="f32", pml_R=0.0, pml_npower=0.0, pml_f0=0.0, device=None, stream=None,
+                 alpha_r=None, mechanisms=None):
+        """alpha_r, mechanisms: frequency-dependent absorption (el_relaxation): the strength
+        cell map (1/s) and the (omega_l, w_l) pairs of the relaxation mechanisms."""
         L = lib()
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
-        self.grid = make_grid(nx, ny, nz, dx, dt, nsteps, npml, precision, pml_R, pml_npower, pml_f0)
+        self.grid = make_grid(nx, ny, nz, dx, dt, nsteps, npml, precision, pml_R, pml_npower, pml_f0,
+                              mechanisms=mechanisms)
+        self.nmech = int(self.grid.relax.nmech)
         self.precision = "f64" if self.grid.precision == EL_F64 else "f32"
         self.dtype = torch.float64 if self.precision == "f64" else torch.float32
         self.shape = (int(nz), int(ny), int(nx))
@@ -185,11 +207,13 @@ class Plan:
         with torch.cuda.device(self.device):
             self.workspace = torch.empty(self.bytes, dtype=torch.uint8, device=self.device)
             maps = [_dev_f32(m, self.device) for m in (lam, mu, rho, alpha)]
-            for m in maps:
+            ar = _dev_f32(alpha_r, self.device) if self.nmech > 0 and alpha_r is not None else None
+            for m in maps + ([ar] if ar is not None else []):
                 assert m.numel() == self.N, "material map size does not match the grid"
             h = ctypes.c_void_p(None)
             st = L.el_plan_create(ctypes.byref(h), ctypes.byref(self.grid),
                                   *[ctypes.c_void_p(m.data_ptr()) for m in maps],
+                                  ctypes.c_void_p(ar.data_ptr() if ar is not None else None),
                                   rec.ctypes.data_as(ctypes.c_void_p), self.nrec,
                                   ctypes.c_void_p(self.workspace.data_ptr()), self.bytes, _stream(stream))
             _check(st)
@@ -198,6 +222,8 @@ class Plan:
 
     @classmethod
     def from_scenario(cls, sc, precision="f32", **kw):
+        if getattr(sc, "mechanisms", None) and "mechanisms" not in kw:
+            kw.update(alpha_r=sc.alpha_r, mechanisms=sc.mechanisms)
         return cls(sc.nx, sc.ny, sc.nz, sc.dx, sc.dt, sc.nsteps, sc.npml, sc.lam, sc.mu, sc.rho,
                    sc.alpha, sc.rec, precision=precision, **kw)
 

@@ -107,3 +107,18 @@ def test_grid_check_rejects_slabs_beyond_32bit_offsets():
     # in double the limit halves
     with pytest.raises(el.ElError):
         el.grid_check(el.make_grid(6900, 6900, 10, 1e-4, 1e-8, 10, 4, precision="f64"))
+
+
+def test_grid_check_relaxation_mechanisms():
+    ok = [(2e6, 0.5), (1e7, 0.5)]
+    el.grid_check(el.make_grid(16, 12, 10, 1e-4, 1e-8, 10, 3, mechanisms=ok))
+    for bad in ([(0.0, 1.0)], [(-1e6, 1.0)], [(1e6, -0.1)], [(float("nan"), 1.0)], [(1e6, float("inf"))],
+                [(1e6, 0.2)] * 5):
+        with pytest.raises(el.ElError) as ei:
+            el.grid_check(el.make_grid(16, 12, 10, 1e-4, 1e-8, 10, 3, mechanisms=bad))
+        assert ei.value.status == el.EL_EINVAL
+    # the memory variables take 3 arrays per mechanism over every tile, plus the strength map
+    b0 = el.plan_bytes(el.make_grid(64, 40, 30, 1e-4, 1e-8, 10, 3), 4)
+    b1 = el.plan_bytes(el.make_grid(64, 40, 30, 1e-4, 1e-8, 10, 3, mechanisms=ok[:1]), 4)
+    b2 = el.plan_bytes(el.make_grid(64, 40, 30, 1e-4, 1e-8, 10, 3, mechanisms=ok), 4)
+    assert b2 - b1 >= 3 * 64 * 40 * 30 * 4 and b1 - b0 >= 4 * 64 * 40 * 30 * 4

@@ -186,6 +186,9 @@ def main():
     ap.add_argument("--no-serving", action="store_true", help="skip the plain vs batched serving comparison")
     ap.add_argument("--no-general", action="store_true",
                     help="skip the general-update measurement (the workload with the fluid update off)")
+    ap.add_argument("--no-fd", action="store_true",
+                    help="skip the frequency-dependent absorption measurement (the workload with relaxation "
+                         "mechanisms in the skull)")
     ap.add_argument("--serving-rates", type=float, nargs="+", default=[2.0, 10.0])
     ap.add_argument("--serving-count", type=int, default=16)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -320,6 +323,48 @@ def main():
         log(f"[bench] general update only: forward {gf_ms:.1f} ms, adjoint {ga_ms:.1f} ms, "
             f"{general['value']:.1f} Gcell-updates/s")
 
+    freqdep = None
+    if not args.no_fd:
+        # the same workload with the skull's absorption given by two relaxation mechanisms
+        # (frequency-dependent absorption): one forward + one adjoint, sampled kernel timing
+        plan = None
+        torch.cuda.empty_cache()
+        t0 = time.time()
+        scf = S.make(args.workload + "fd", **over)
+        planf = el.Plan.from_scenario(scf)
+        rtiles, rcells, rpoints = planf.relaxation_extent()
+        log(f"[bench] {scf.name}: {len(scf.mechanisms)} mechanisms, relaxation on {rtiles} tiles, {rpoints} "
+            f"velocity points (set up in {time.time() - t0:.1f}s)")
+        p0f = torch.from_numpy(scf.p0).to(dev)
+        planf.forward(p0f, out=traces)
+        torch.cuda.synchronize()
+        planf.timing(True, every=args.timing_every)
+        f0, f1, f2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        f0.record()
+        planf.forward(p0f, out=traces)
+        f1.record()
+        planf.adjoint(traces, out=padj)
+        f2.record()
+        torch.cuda.synchronize()
+        planf.timing(False)
+        fk = planf.kernel_times()
+        ff_ms, fa_ms = f0.elapsed_time(f1), f1.elapsed_time(f2)
+        n_r, ms_r = fk.get("relax", (0, 0.0))
+        rb = bytemodel.relax_bytes(rcells, rpoints, len(scf.mechanisms), 4)
+        r_us = ms_r / max(n_r, 1) * 1e3
+        freqdep = {"workload": f"{scf.name}: the skull's absorption as relaxation mechanisms "
+                               f"{[(round(o / 2 / 3.141592653589793 / 1e6, 3), w) for o, w in scf.mechanisms]} "
+                               f"(MHz, weight), water diffusive",
+                   "value": 2 * upd / ((ff_ms + fa_ms) / 1e3) / 1e9, "unit": "Gcell-updates/s",
+                   "ms_per_step": ff_ms + fa_ms, "fwd_ms": ff_ms, "adj_ms": fa_ms,
+                   "relax": {"tiles": rtiles, "cells": rcells, "points": rpoints, "launches": n_r, "avg_us": r_us,
+                             "bytes_per_launch": rb, "gbs": rb / (r_us / 1e6) / 1e9 if n_r else None},
+                   "kernels_us": {k: v[1] / v[0] * 1e3 for k, v in fk.items() if v[0]}}
+        log(f"[bench] frequency-dependent: forward {ff_ms:.1f} ms, adjoint {fa_ms:.1f} ms, "
+            f"{freqdep['value']:.1f} Gcell-updates/s; relaxation {r_us:.1f} us/launch")
+        del planf, p0f
+        torch.cuda.empty_cache()
+
     serving = None
     if not args.no_serving:
         from paper_1709_02733_amd import serving as SV
@@ -366,6 +411,7 @@ def main():
         "roofline": roofline,
         "kernels": {k: {"avg_us": v["avg_us"], "gbs": v["gbs"], "launches": v["launches"]} for k, v in per.items()},
         "general_path": general,
+        "frequency_dependent": freqdep,
         "serving": serving,
         "cpu_baseline": cpu,
     }

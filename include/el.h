@@ -279,6 +279,15 @@ el_status el_plan_field(el_plan plan, int32_t id, void **ptr, size_t *count);
  */
 el_status el_plan_layout(el_plan plan, int64_t *row_pitch, int64_t *plane_pitch, int64_t *origin);
 
+/*
+ * Extent of the relaxation sub-update (el_relaxation): the stencil tiles it
+ * visits, those holding a velocity point with beta > 0, their cells, and the
+ * (cell, component) velocity points with beta > 0, which it updates.  All
+ * zero for a plan without relaxation mechanisms.  Any pointer may be NULL.
+ * Host-only.
+ */
+el_status el_plan_relaxation(el_plan plan, int64_t *tiles, int64_t *cells, int64_t *points);
+
 /* Number of cells N, receivers L and trace samples M of a plan. */
 el_status el_plan_sizes(el_plan plan, int64_t *ncells, int32_t *nrec, int32_t *nsteps);
 

@@ -78,3 +78,10 @@ def step_bytes(op: str, nx, ny, nz, npml, nrec, es=4, fluid_cells: int = 0, flui
         ks = ("adj_velocity", "adj_stress", "scatter")
     return sum(kernel_bytes(k, nx, ny, nz, npml, nrec, es, fluid_cells, fluid_layer_cells, skipped_stores,
                             uniform_cells) for k in ks)
+
+
+def relax_bytes(cells: int, points: int, nmech: int, es: int = 4) -> float:
+    """Algorithmic bytes of one relaxation launch (frequency-dependent absorption): the
+    strength map alpha_r read once per cell of the tiles it visits, and per velocity point with
+    beta > 0 (el_plan_relaxation) the velocity and the nmech memory variables read and written."""
+    return float(cells * es + points * (2 + 2 * nmech) * es)

@@ -106,6 +106,8 @@ bool layout(const el_grid &g, int nrec, Layout *L) {
         const int nm = g.relax.nmech;
         L->relax_map = nm > 0 ? take(N * es) : 0;
         L->relax_flag = nm > 0 ? take((size_t)t.ntiles) : 0;
+        L->relax_count = nm > 0 ? take((size_t)t.ntiles * sizeof(int)) : 0;
+        L->relax_order = nm > 0 ? take((size_t)8 * t.per * sizeof(int)) : 0;
         L->relax_zeta = nm > 0 ? take((size_t)t.ntiles * 3 * nm * t.zc * kTileX * kTileY * es) : 0;
     }
     L->partial = take(kStats * kDotBlocks * 8);
@@ -343,6 +345,7 @@ void bind_relax(Relax<T> &r, el_plan_ *p) {
         r.ar = reinterpret_cast<T *>(p->ws + p->L.relax_map);
         r.zeta = reinterpret_cast<T *>(p->ws + p->L.relax_zeta);
         r.flag = reinterpret_cast<unsigned char *>(p->ws + p->L.relax_flag);
+        r.count = reinterpret_cast<int *>(p->ws + p->L.relax_count);
     }
 }
 
@@ -642,10 +645,40 @@ el_status el_plan_create(el_plan *out, const el_grid *grid, const float *lam, co
     if (st != EL_OK) return bail(st);
     if (grid->relax.nmech > 0 && p->tiles.ntiles > 0) {
         std::vector<unsigned char> rflag(p->tiles.ntiles, 0);
+        std::vector<int> rcount(p->tiles.ntiles, 0);
         e = hipMemcpyAsync(rflag.data(), p->ws + L.relax_flag, rflag.size(), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(rcount.data(), p->ws + L.relax_count, rcount.size() * sizeof(int), hipMemcpyDeviceToHost, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         if (e != hipSuccess) return bail(hip_fail(e, "relaxation tiles"));
-        for (unsigned char f : rflag) p->relax_tiles += f;
+        const Tiles &t = p->tiles;
+        for (int q = 0; q < t.ntiles; ++q) {
+            if (!rflag[q]) continue;
+            const int bx = q % t.ntx, r = q / t.ntx, by = r % t.nty, bz = r / t.nty;
+            p->relax_tiles += 1;
+            p->relax_points += rcount[q];
+            p->relax_cells += (long long)std::min(kTileX, grid->nx - bx * kTileX) * std::min(kTileY, grid->ny - by * kTileY) *
+                              std::min(t.zc, grid->nz - bz * t.zc);
+        }
+        // launch order of the relaxation: the flagged tiles of XCD x (in z-major order) at blocks
+        // x, x + 8, x + 16, ..., padded with -1
+        std::vector<std::vector<int>> per_xcd(8);
+        for (int q = 0; q < t.ntiles; ++q)
+            if (rflag[q]) per_xcd[tile_xcd(t, q)].push_back(q);
+        size_t most = 0;
+        for (auto &v : per_xcd) most = std::max(most, v.size());
+        std::vector<int> rorder(8 * most, -1);
+        for (int x = 0; x < 8; ++x)
+            for (size_t n = 0; n < per_xcd[x].size(); ++n) rorder[8 * n + x] = per_xcd[x][n];
+        int *dst = reinterpret_cast<int *>(p->ws + L.relax_order);
+        if (!rorder.empty()) {
+            e = hipMemcpyAsync(dst, rorder.data(), rorder.size() * sizeof(int), hipMemcpyHostToDevice, s);
+            if (e == hipSuccess) e = hipStreamSynchronize(s);
+            if (e != hipSuccess) return bail(hip_fail(e, "relaxation order"));
+        }
+        p->rf.order = dst;
+        p->rd.order = dst;
+        p->rf.nblocks = p->rd.nblocks = (int)rorder.size();
     }
     st = upload_receivers(p, rec, s);
     if (st != EL_OK) return bail(st);
@@ -884,6 +917,14 @@ el_status el_plan_fluid_path(el_plan p, int32_t enable, el_fluid_stats *stats) {
             stats->uniform_cells = p->uniform_cells;
         }
     }
+    return EL_OK;
+}
+
+el_status el_plan_relaxation(el_plan p, int64_t *tiles, int64_t *cells, int64_t *points) {
+    if (!p) return fail(EL_EINVAL, "plan is NULL");
+    if (tiles) *tiles = p->relax_tiles;
+    if (cells) *cells = p->relax_cells;
+    if (points) *points = p->relax_points;
     return EL_OK;
 }
 

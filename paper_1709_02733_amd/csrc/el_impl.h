@@ -155,6 +155,10 @@ struct Relax {
     T *zeta;                 // [tile][l][component][plane of the chunk][row][column]: kTileX * kTileY
                              // * zc values per (tile, l, component)
     const unsigned char *flag;   // per tile: 1 if some velocity point of it has beta > 0
+    int *count;              // per tile: its (cell, component) velocity points with beta > 0 (set-up)
+    const int *order;        // flagged tile of each block of the relaxation launch (-1: none);
+                             // block b runs on XCD b mod 8, which holds the tile (tile_xcd)
+    int nblocks;             // blocks of the relaxation launch
 };
 
 // Receiver tables (cell offsets are padded element indices).
@@ -216,6 +220,8 @@ struct Layout {
                              // kinetic and potential part of each tile block
     size_t relax_map;        // alpha_r (padded cell map), with relaxation mechanisms only
     size_t relax_flag;       // per tile: relaxation applies
+    size_t relax_count;      // per tile: velocity points with beta > 0 (int)
+    size_t relax_order;      // flagged tile of each block of the relaxation launch (int)
     size_t relax_zeta;       // memory variables of the relaxation mechanisms (Relax::zeta)
     size_t total;
 };
@@ -289,6 +295,8 @@ struct el_plan_ {
     el::Relax<float> rf;               // relaxation mechanisms (L = 0: none)
     el::Relax<double> rd;
     long long relax_tiles = 0;         // tiles the relaxation sub-update visits
+    long long relax_cells = 0;         // and their cells
+    long long relax_points = 0;        // (cell, component) velocity points with beta > 0
     el::Rec rec;
     el::Tiles tiles;
     std::vector<unsigned char> fast;   // per tile: the fluid update applies (host copy)

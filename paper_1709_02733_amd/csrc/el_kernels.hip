@@ -543,24 +543,36 @@ __global__ void k_relax_map(Dev<T> d, const float *ar, T *dst, long long total) 
     }
 }
 
-// Tile q is flagged when alpha_r > 0 on one of its cells or on their +x, +y, +z neighbours
-// (the cells whose means give beta at the tile's velocity points).
+// Tile q is flagged when some velocity point of it has beta > 0 (the mean of alpha_r over the
+// point's two cells, the upper one edge-replicated); count[q] receives the number of such
+// (cell, component) points.
 template <typename T>
-__global__ __launch_bounds__(256) void k_relax_flags(Dev<T> d, Tiles tl, const T *ar, unsigned char *flag) {
+__global__ __launch_bounds__(256) void k_relax_flags(Dev<T> d, Tiles tl, const T *ar, unsigned char *flag,
+                                                     int *count) {
     const int q = blockIdx.x;
     if (q >= tl.ntiles) return;
     const int bx = q % tl.ntx, r = q / tl.ntx, by = r % tl.nty, bz = r / tl.nty;
     const int x0 = bx * kTileX, y0 = by * kTileY, z0 = bz * tl.zc;
-    const int w = min(kTileX, d.nx - x0) + 1, hgt = min(kTileY, d.ny - y0) + 1, dep = min(tl.zc, d.nz - z0) + 1;
-    int any = 0;
+    const int w = min(kTileX, d.nx - x0), hgt = min(kTileY, d.ny - y0), dep = min(tl.zc, d.nz - z0);
+    const long long stride[3] = {1, d.px, d.plane};
+    int n = 0;
     for (long long e = threadIdx.x; e < (long long)w * hgt * dep; e += blockDim.x) {
         const int xx = x0 + (int)(e % w);
         const long long rr = e / w;
         const int yy = y0 + (int)(rr % hgt), zz = z0 + (int)(rr / hgt);
-        if (ar[(long long)(zz + 2) * d.plane + (long long)yy * d.px + xx] > T(0)) any = 1;
+        const long long c = (long long)(zz + 2) * d.plane + (long long)yy * d.px + xx;
+        for (int a = 0; a < 3; ++a)
+            if (T(0.5) * (ar[c] + ar[c + stride[a]]) > T(0)) ++n;
     }
-    any = __syncthreads_or(any);
-    if (threadIdx.x == 0) flag[q] = any ? 1 : 0;
+    __shared__ int total;
+    if (threadIdx.x == 0) total = 0;
+    __syncthreads();
+    if (n) atomicAdd(&total, n);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        flag[q] = total > 0 ? 1 : 0;
+        count[q] = total;
+    }
 }
 
 template <typename T>
@@ -571,7 +583,7 @@ hipError_t launch_relax_setup(const Dev<T> &d, const Tiles &tl, const float *ar_
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || tl.ntiles == 0) return e;
     hipLaunchKernelGGL(k_relax_flags<T>, dim3(tl.ntiles), dim3(256), 0, s, d, tl, r.ar,
-                       const_cast<unsigned char *>(r.flag));
+                       const_cast<unsigned char *>(r.flag), r.count);
     return hipGetLastError();
 }
 
@@ -592,61 +604,113 @@ hipError_t launch_relax_zero(const Tiles &tl, const Relax<T> &r, hipStream_t s) 
     return hipGetLastError();
 }
 
-// The sub-update R (ADJ: R^T) on the tile of each block of the stencil grid (same order table).
-template <typename T, bool ADJ>
+// The sub-update R (ADJ: R^T) on the flagged tile of each block (Relax::order).  The strengths
+// of a plane (the cell's and its +x, +y, +z neighbours') are loaded two planes ahead, the
+// velocities and memory variables one plane ahead and only for the components with beta > 0
+// (most cells of a flagged tile have none: the loads are masked off per lane), so the loads
+// of two planes are in flight while one is computed.
+template <typename T, bool ADJ, int L>
 __global__ __launch_bounds__(256) void k_relax(Dev<T> d, Tiles tl, Relax<T> r) {
-    const int ent = tl.order[blockIdx.x];
-    if (ent < 0) return;
-    const int q = ent & kTileMask;
-    if (!r.flag[q]) return;
+    const int q = r.order[blockIdx.x];
+    if (q < 0) return;
     const int bx = q % tl.ntx, rr = q / tl.ntx, by = rr % tl.nty, bz = rr / tl.nty;
     const int col = (int)threadIdx.x % kTileX, row = (int)threadIdx.x / kTileX;
     const int i = bx * kTileX + col, j = by * kTileY + row, z0 = bz * tl.zc;
     if (i >= d.nx || j >= d.ny) return;
     const int z1 = min(z0 + tl.zc, d.nz);
-    const long long stride[3] = {1, d.px, d.plane};
     const long long per_c = (long long)tl.zc * kTileX * kTileY;       // one (l, component) of a tile
-    T *zt = r.zeta + (long long)q * 3 * r.L * per_c + (long long)row * kTileX + col;
+    T *zt = r.zeta + (long long)q * 3 * L * per_c + (long long)row * kTileX + col;
     const T dt = d.dt;
-    for (int k = z0; k < z1; ++k) {
+    struct Coef {
+        T a[4];          // alpha_r at the cell and at its +x, +y, +z neighbours
+    };
+    struct Plane {
+        T u[3];
+        T z[L][3];
+    };
+    auto load_coef = [&](Coef &p, int k) {
+        const long long e = (long long)(k + 2) * d.plane + (long long)j * d.px + i;
+        p.a[0] = r.ar[e];
+        p.a[1] = r.ar[e + 1];
+        p.a[2] = r.ar[e + d.px];
+        p.a[3] = r.ar[e + d.plane];
+    };
+    auto load = [&](Plane &p, const Coef &cf, int k) {
         const long long e = (long long)(k + 2) * d.plane + (long long)j * d.px + i;
         const long long zk = (long long)(k - z0) * kTileX * kTileY;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            const T beta = T(0.5) * (r.ar[e] + r.ar[e + stride[c]]);
-            if (!(beta > T(0))) continue;          // R is the identity here (and R^T, with z = 0)
-            T bl[EL_MAX_MECH], zl[EL_MAX_MECH];
-            T B = T(0);
-            for (int l = 0; l < r.L; ++l) {
-                bl[l] = r.w[l] * beta;
-                B += bl[l];
-                zl[l] = zt[((long long)l * 3 + c) * per_c + zk];
-            }
-            const T a = T(1) / (T(1) + dt * B);
-            T *u = d.f[U1 + c] + e;
-            if (!ADJ) {
-                T acc = *u;
-                for (int l = 0; l < r.L; ++l) acc += dt * bl[l] * zl[l];
-                const T un = acc * a;
-                *u = un;
-                for (int l = 0; l < r.L; ++l)
-                    zt[((long long)l * 3 + c) * per_c + zk] = r.c[l] * zl[l] + (T(1) - r.c[l]) * un;
-            } else {
-                T sum = *u;
-                for (int l = 0; l < r.L; ++l) sum += (T(1) - r.c[l]) * zl[l];
-                *u = a * sum;
-                for (int l = 0; l < r.L; ++l) zt[((long long)l * 3 + c) * per_c + zk] = dt * bl[l] * a * sum + r.c[l] * zl[l];
+            const bool on = cf.a[0] + cf.a[1 + c] > T(0);
+            p.u[c] = on ? d.f[U1 + c][e] : T(0);
+#pragma unroll
+            for (int l = 0; l < L; ++l) p.z[l][c] = on ? zt[((long long)l * 3 + c) * per_c + zk] : T(0);
+        }
+    };
+    Coef c_cur, c_nxt{}, c_nn{};
+    Plane cur, nxt;
+    load_coef(c_cur, z0);
+    if (z0 + 1 < z1) load_coef(c_nxt, z0 + 1);
+    load(cur, c_cur, z0);
+    for (int k = z0; k < z1; ++k) {
+        if (k + 2 < z1) load_coef(c_nn, k + 2);
+        if (k + 1 < z1) load(nxt, c_nxt, k + 1);
+        __builtin_amdgcn_sched_barrier(0);
+        const long long e = (long long)(k + 2) * d.plane + (long long)j * d.px + i;
+        const long long zk = (long long)(k - z0) * kTileX * kTileY;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const T beta = T(0.5) * (c_cur.a[0] + c_cur.a[1 + c]);
+            if (beta > T(0)) {                     // else R is the identity (and R^T, with z = 0)
+                T bl[L];
+                T B = T(0);
+#pragma unroll
+                for (int l = 0; l < L; ++l) {
+                    bl[l] = r.w[l] * beta;
+                    B += bl[l];
+                }
+                const T a = T(1) / (T(1) + dt * B);
+                if (!ADJ) {
+                    T acc = cur.u[c];
+#pragma unroll
+                    for (int l = 0; l < L; ++l) acc += dt * bl[l] * cur.z[l][c];
+                    const T un = acc * a;
+                    d.f[U1 + c][e] = un;
+#pragma unroll
+                    for (int l = 0; l < L; ++l)
+                        zt[((long long)l * 3 + c) * per_c + zk] = r.c[l] * cur.z[l][c] + (T(1) - r.c[l]) * un;
+                } else {
+                    T sum = cur.u[c];
+#pragma unroll
+                    for (int l = 0; l < L; ++l) sum += (T(1) - r.c[l]) * cur.z[l][c];
+                    d.f[U1 + c][e] = a * sum;
+#pragma unroll
+                    for (int l = 0; l < L; ++l)
+                        zt[((long long)l * 3 + c) * per_c + zk] = dt * bl[l] * a * sum + r.c[l] * cur.z[l][c];
+                }
             }
         }
+        cur = nxt;
+        c_cur = c_nxt;
+        c_nxt = c_nn;
     }
+}
+
+template <typename T, bool ADJ>
+hipError_t launch_relax_l(const Dev<T> &d, const Tiles &tl, const Relax<T> &r, hipStream_t s) {
+    const dim3 g(r.nblocks), b(256);
+    switch (r.L) {
+        case 1: hipLaunchKernelGGL((k_relax<T, ADJ, 1>), g, b, 0, s, d, tl, r); break;
+        case 2: hipLaunchKernelGGL((k_relax<T, ADJ, 2>), g, b, 0, s, d, tl, r); break;
+        case 3: hipLaunchKernelGGL((k_relax<T, ADJ, 3>), g, b, 0, s, d, tl, r); break;
+        default: hipLaunchKernelGGL((k_relax<T, ADJ, 4>), g, b, 0, s, d, tl, r); break;
+    }
+    return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_relax(const Dev<T> &d, const Tiles &tl, const Relax<T> &r, bool adjoint, hipStream_t s) {
-    if (r.L == 0) return hipSuccess;
-    if (adjoint) hipLaunchKernelGGL((k_relax<T, true>), dim3(8 * tl.per), dim3(256), 0, s, d, tl, r);
-    else hipLaunchKernelGGL((k_relax<T, false>), dim3(8 * tl.per), dim3(256), 0, s, d, tl, r);
-    return hipGetLastError();
+    if (r.L == 0 || r.nblocks == 0) return hipSuccess;
+    return adjoint ? launch_relax_l<T, true>(d, tl, r, s) : launch_relax_l<T, false>(d, tl, r, s);
 }
 
 // ------------------------------------------------------ inner products

@@ -56,7 +56,8 @@ _lib = None
 EXPORTS = ("el_version", "el_status_string", "el_last_error", "el_grid_check", "el_plan_bytes",
            "el_plan_create", "el_plan_destroy", "el_forward", "el_forward_energy", "el_adjoint", "el_dot_f64",
            "el_dot_f64_noalloc", "el_eir_apply",
-           "el_plan_field", "el_plan_layout", "el_plan_sizes", "el_plan_fluid_path", "el_plan_timing",
+           "el_plan_field", "el_plan_layout", "el_plan_sizes", "el_plan_relaxation", "el_plan_fluid_path",
+           "el_plan_timing",
            "el_plan_kernel_time",
            "el_exec_create", "el_exec_destroy", "el_exec_start", "el_exec_poll", "el_exec_wait", "el_exec_slots")
 KERNELS = ("velocity", "stress", "adj_velocity", "adj_stress", "gather", "scatter", "relax")
@@ -102,6 +103,9 @@ def lib():
                                      ctypes.POINTER(ctypes.c_int64)]
         L.el_plan_sizes.restype = st
         L.el_plan_sizes.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(i32), ctypes.POINTER(i32)]
+        L.el_plan_relaxation.restype = st
+        L.el_plan_relaxation.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
+                                         ctypes.POINTER(ctypes.c_int64)]
         L.el_plan_fluid_path.restype = st
         L.el_plan_fluid_path.argtypes = [vp, i32, ctypes.POINTER(FluidStats)]
         L.el_plan_timing.restype = st
@@ -304,6 +308,13 @@ class Plan:
         flag = -1 if enable is None else (1 if enable else 0)
         _check(lib().el_plan_fluid_path(self._h, flag, ctypes.byref(st)))
         return {name: int(getattr(st, name)) for name, _ in FluidStats._fields_}
+
+    def relaxation_extent(self) -> tuple[int, int, int]:
+        """(tiles, cells, points): the tiles the relaxation sub-update visits, their cells, and
+        the (cell, component) velocity points it updates (el_plan_relaxation)."""
+        t, c, p = ctypes.c_int64(0), ctypes.c_int64(0), ctypes.c_int64(0)
+        _check(lib().el_plan_relaxation(self._h, ctypes.byref(t), ctypes.byref(c), ctypes.byref(p)))
+        return int(t.value), int(c.value), int(p.value)
 
     def timing(self, enable: bool = True, every: int = 1):
         """Record an event pair around the time-loop kernel launches of every `every`-th time

@@ -93,6 +93,7 @@ def test_zero_strength_is_bitwise_the_diffusive_plan():
     sc = S.random_scenario((23, 19, 17), seed=5, nsteps=30, npml=3, nrec=9)
     base = el.Plan.from_scenario(sc)
     rel = el.Plan.from_scenario(sc, alpha_r=np.zeros(sc.shape, np.float32), mechanisms=MECH)
+    assert rel.relaxation_extent() == (0, 0, 0) and base.relaxation_extent() == (0, 0, 0)
     p0 = torch.from_numpy(sc.p0)
     tr0, tr1 = base.forward(p0), rel.forward(p0)
     assert torch.equal(tr0, tr1)
@@ -139,6 +140,15 @@ def test_skull_medium_with_frequency_dependent_absorption():
     sc = S.skull_scenario(n=128, nsteps=200, nrec=256, frequency_dependent=True)
     assert sc.mechanisms and np.any(sc.alpha_r > 0)
     plan = el.Plan.from_scenario(sc)
+    # extent: every velocity point whose two cells hold some strength, counted by hand here
+    ar = sc.alpha_r.astype(np.float64)
+    points = 0
+    for ax in (2, 1, 0):                       # x, y, z of the [z][y][x] map; upper cell replicated
+        nb = np.concatenate([np.take(ar, np.arange(1, ar.shape[ax]), axis=ax),
+                             np.take(ar, [ar.shape[ax] - 1], axis=ax)], axis=ax)
+        points += int(np.count_nonzero(0.5 * (ar + nb) > 0))
+    tiles, cells, pts = plan.relaxation_extent()
+    assert pts == points and 0 < tiles and pts <= 3 * cells
     ref = Model.from_scenario(sc)
     tr = plan.forward(torch.from_numpy(sc.p0)).cpu().numpy()
     tr_ref = ref.forward(sc.p0.astype(np.float64))

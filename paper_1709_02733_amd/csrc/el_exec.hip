@@ -4,8 +4,8 @@
 // operation on a slot enqueues all of it at once: the initial state (direct
 // launches), then the time loop as replays of a captured graph of K steps,
 // then the final extraction.  The trace row of each step comes from a device
-// counter that the receiver kernel advances, so the same K-step graph is valid
-// for every chunk.  Operations on different slots run concurrently on the
+// counter that the step's own kernels advance, so the same K-step graph is
+// valid for every chunk.  Operations on different slots run concurrently on the
 // device; the host only polls completion events, so it is free to build the
 // next plans while the GPU works.  Results are identical to el_forward /
 // el_adjoint on the same plan: the same kernels run in the same order.
@@ -46,20 +46,23 @@ el_status hipf(hipError_t e, const char *what) {
         if (e_ != hipSuccess) return hipf(e_, what); \
     } while (0)
 
+// One time step with the trace row taken from the device counter: the forward velocity pass
+// gathers row *ctr (the stresses of the previous step) in extra blocks and the stress pass
+// advances the counter; the adjoint velocity pass steps it back and the scatter after the
+// adjoint stress pass reads that row.
 template <typename T>
 hipError_t launch_step(el_plan p, const Dev<T> &d, int op, void *traces, int *ctr, hipStream_t s) {
     hipError_t e;
     const Relax<T> &rx = plan_relax<T>(p);
     if (op == EL_OP_FORWARD) {
-        e = launch_velocity(d, p->tiles, s);
+        e = launch_velocity(d, p->tiles, s, &p->rec, static_cast<double *>(traces), nullptr, ctr);
         if (e == hipSuccess) e = launch_relax(d, p->tiles, rx, false, s);
-        if (e == hipSuccess) e = launch_stress(d, p->tiles, s);
-        if (e == hipSuccess) e = launch_gather_ctr(d, p->rec, static_cast<double *>(traces), ctr, s);
+        if (e == hipSuccess) e = launch_stress(d, p->tiles, s, ctr);
     } else {
-        e = launch_adj_velocity(d, p->tiles, s);
+        e = launch_adj_velocity(d, p->tiles, s, ctr);
         if (e == hipSuccess) e = launch_relax(d, p->tiles, rx, true, s);
         if (e == hipSuccess) e = launch_adj_stress(d, p->tiles, s);
-        if (e == hipSuccess) e = launch_scatter_ctr(d, p->rec, static_cast<const double *>(traces), ctr, s);
+        if (e == hipSuccess) e = launch_scatter(d, p->rec, static_cast<const double *>(traces), s, ctr);
     }
     return e;
 }
@@ -97,11 +100,10 @@ el_status start_op(el_exec ex, ExecSlot &sl, el_plan p, const Dev<T> &d, int op,
     EX_TRY(launch_relax_zero(p->tiles, plan_relax<T>(p), s), "relaxation state");
     if (op == EL_OP_FORWARD) {
         EX_TRY(launch_inject(d, static_cast<const T *>(in), s), "inject");
-        EX_TRY(launch_gather(d, p->rec, static_cast<double *>(out), s), "gather");
-        EX_TRY(launch_set_counter(ctr, 1, s), "counter");
+        EX_TRY(launch_set_counter(ctr, 0, s), "counter");
     } else {
         EX_TRY(launch_scatter(d, p->rec, static_cast<const double *>(in) + (size_t)(M - 1) * L, s), "scatter");
-        EX_TRY(launch_set_counter(ctr, M - 2, s), "counter");
+        EX_TRY(launch_set_counter(ctr, M - 1, s), "counter");
     }
     const int nupd = M - 1;
     const int K = nupd < ex->chunk ? nupd : ex->chunk;
@@ -117,6 +119,8 @@ el_status start_op(el_exec ex, ExecSlot &sl, el_plan p, const Dev<T> &d, int op,
     }
     for (int c = 0; c < nfull; ++c) EX_TRY(hipGraphLaunch(sl.graph[0], s), "graph launch");
     if (rem > 0) EX_TRY(hipGraphLaunch(sl.graph[1], s), "graph launch");
+    if (op == EL_OP_FORWARD)
+        EX_TRY(launch_gather(d, p->rec, static_cast<double *>(out) + (size_t)(M - 1) * L, s), "gather");
     if (p->fluid_path && p->fast_tiles > 0) EX_TRY(launch_fluid_fill(d, p->tiles, s), "fluid fill");
     if (op == EL_OP_ADJOINT) EX_TRY(launch_extract(d, static_cast<T *>(out), s), "extract");
     EX_TRY(hipEventRecord(p->done, s), "record plan completion");

@@ -247,17 +247,22 @@ template <typename T> hipError_t launch_inject(const Dev<T> &d, const T *p0, hip
 // thread of every tile block (8 * per * kTileX * kTileY doubles); launch_energy_pot writes the
 // potential part, one double per tile block; launch_energy_final sums the threads' parts per
 // block into kin_block, then everything into *out.
+// ctr != null (captured step graphs): a device step counter.  The velocity launch gathers row
+// *ctr of the traces at grow and the stress launch then advances the counter; the adjoint
+// velocity launch steps it back by one and the scatter then reads row *ctr of the traces at y.
 template <typename T> hipError_t launch_velocity(const Dev<T> &d, const Tiles &tl, hipStream_t s,
                                                  const Rec *r = nullptr, double *grow = nullptr,
-                                                 double *epart = nullptr);
+                                                 double *epart = nullptr, int *ctr = nullptr);
 template <typename T> hipError_t launch_energy_pot(const Dev<T> &d, const Tiles &tl, double *epart, hipStream_t s);
 hipError_t launch_energy_final(const double *kin_thread, double *kin_block, const double *pot, int nb, double *out,
                                hipStream_t s);
-template <typename T> hipError_t launch_stress(const Dev<T> &d, const Tiles &tl, hipStream_t s);
+template <typename T> hipError_t launch_stress(const Dev<T> &d, const Tiles &tl, hipStream_t s, int *ctr = nullptr);
 template <typename T> hipError_t launch_gather(const Dev<T> &d, const Rec &r, double *trace_row, hipStream_t s);
-template <typename T> hipError_t launch_adj_velocity(const Dev<T> &d, const Tiles &tl, hipStream_t s);
+template <typename T> hipError_t launch_adj_velocity(const Dev<T> &d, const Tiles &tl, hipStream_t s,
+                                                     int *ctr = nullptr);
 template <typename T> hipError_t launch_adj_stress(const Dev<T> &d, const Tiles &tl, hipStream_t s);
-template <typename T> hipError_t launch_scatter(const Dev<T> &d, const Rec &r, const double *y_row, hipStream_t s);
+template <typename T> hipError_t launch_scatter(const Dev<T> &d, const Rec &r, const double *y, hipStream_t s,
+                                                const int *ctr = nullptr);
 template <typename T> hipError_t launch_extract(const Dev<T> &d, T *p, hipStream_t s);
 template <typename T> hipError_t launch_fluid_fill(const Dev<T> &d, const Tiles &tl, hipStream_t s);
 hipError_t launch_eir(const double *h, int nh, const double *in, double *out, int M, int L, int transpose,
@@ -275,10 +280,6 @@ template <typename T> hipError_t launch_relax_setup(const Dev<T> &d, const Tiles
 template <typename T> hipError_t launch_relax_zero(const Tiles &tl, const Relax<T> &r, hipStream_t s);
 template <typename T> hipError_t launch_relax(const Dev<T> &d, const Tiles &tl, const Relax<T> &r, bool adjoint,
                                               hipStream_t s);
-template <typename T> hipError_t launch_gather_ctr(const Dev<T> &d, const Rec &r, double *traces, int *ctr,
-                                                   hipStream_t s);
-template <typename T> hipError_t launch_scatter_ctr(const Dev<T> &d, const Rec &r, const double *traces, int *ctr,
-                                                    hipStream_t s);
 
 }  // namespace el
 

@@ -324,32 +324,25 @@ hipError_t launch_gather(const Dev<T> &d, const Rec &r, double *row, hipStream_t
     return hipGetLastError();
 }
 
-// s_kk += Theta^T y_m at the touched cells (entries summed in a fixed order).  With the
-// adjoint stress kept as w = C s this adds (3 lambda + 2 mu) delta to w11, w22, w33, and the
-// normal adjoint memory variables, which hold a (b psi~ + dt w) for the coming step, receive
-// a dt times the same increment.
 template <typename T>
 __device__ __forceinline__ void scatter_point(const Dev<T> &d, const Rec &r, const double *y, int t);
 
+// ctr != null (captured step graphs): y is the whole trace array and the row is *ctr (the
+// adjoint velocity launch before it has stepped the counter back), so one graph of K steps
+// serves every chunk of the time loop.
 template <typename T>
-__global__ void k_scatter(Dev<T> d, Rec r, const double *y) {
+__global__ void k_scatter(Dev<T> d, Rec r, const double *y, const int *ctr) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= r.npts) return;
-    scatter_point(d, r, y, t);
+    scatter_point(d, r, ctr ? y + (size_t)(*ctr) * r.nrec : y, t);
 }
 
 template <typename T>
-hipError_t launch_scatter(const Dev<T> &d, const Rec &r, const double *y, hipStream_t s) {
+hipError_t launch_scatter(const Dev<T> &d, const Rec &r, const double *y, hipStream_t s, const int *ctr) {
     if (r.npts == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_scatter<T>, dim3((r.npts + 255) / 256), dim3(256), 0, s, d, r, y);
+    hipLaunchKernelGGL(k_scatter<T>, dim3((r.npts + 255) / 256), dim3(256), 0, s, d, r, y, ctr);
     return hipGetLastError();
 }
-
-// ------------------------------------------- receivers with a device step counter
-//
-// Variants used inside captured step graphs: the trace row is read from a device counter
-// that the kernel advances when it is done, so one graph of K steps can be replayed.
-// Both run as one block that loops over its work.
 
 __global__ void k_set_counter(int *ctr, int v) {
     if (threadIdx.x == 0 && blockIdx.x == 0) *ctr = v;
@@ -360,31 +353,10 @@ hipError_t launch_set_counter(int *ctr, int v, hipStream_t s) {
     return hipGetLastError();
 }
 
-template <typename T>
-__global__ __launch_bounds__(1024) void k_gather_ctr(Dev<T> d, Rec r, double *traces, int *ctr) {
-    const int row = *ctr;
-    double *out = traces + (size_t)row * r.nrec;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int c = lane & 7;
-    for (int l0 = 0; l0 < r.nrec; l0 += 16 * 8) {
-        const int l = l0 + wave * 8 + (lane >> 3);
-        double v = 0.0;
-        if (l < r.nrec) v = r.w[8 * l + c] * trace_at(d, r, 8 * l + c);
-        v += __shfl_xor(v, 1);
-        v += __shfl_xor(v, 2);
-        v += __shfl_xor(v, 4);
-        if (l < r.nrec && c == 0) out[l] = -v;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) *ctr = row + 1;
-}
-
-template <typename T>
-hipError_t launch_gather_ctr(const Dev<T> &d, const Rec &r, double *traces, int *ctr, hipStream_t s) {
-    hipLaunchKernelGGL(k_gather_ctr<T>, dim3(1), dim3(1024), 0, s, d, r, traces, ctr);
-    return hipGetLastError();
-}
-
+// s_kk += Theta^T y_m at point t of the grid-point-major table (entries summed in a fixed
+// order).  With the adjoint stress kept as w = C s this adds (3 lambda + 2 mu) delta to w11,
+// w22, w33, and the normal adjoint memory variables, which hold a (b psi~ + dt w) for the
+// coming step, receive a dt times the same increment.
 template <typename T>
 __device__ __forceinline__ void scatter_point(const Dev<T> &d, const Rec &r, const double *y, int t) {
     double acc = 0.0;
@@ -406,21 +378,6 @@ __device__ __forceinline__ void scatter_point(const Dev<T> &d, const Rec &r, con
             if (tw >= 0) g[slab_byte(d, a, tw, crd[0], crd[1], crd[2]) / sizeof(T)] += inc;
         }
     }
-}
-
-template <typename T>
-__global__ __launch_bounds__(1024) void k_scatter_ctr(Dev<T> d, Rec r, const double *traces, int *ctr) {
-    const int row = *ctr;
-    const double *y = traces + (size_t)row * r.nrec;
-    for (int t = threadIdx.x; t < r.npts; t += blockDim.x) scatter_point(d, r, y, t);
-    __syncthreads();
-    if (threadIdx.x == 0) *ctr = row - 1;
-}
-
-template <typename T>
-hipError_t launch_scatter_ctr(const Dev<T> &d, const Rec &r, const double *traces, int *ctr, hipStream_t s) {
-    hipLaunchKernelGGL(k_scatter_ctr<T>, dim3(1), dim3(1024), 0, s, d, r, traces, ctr);
-    return hipGetLastError();
 }
 
 // p_adj = tau'^T v_0 = -(s11 + s22 + s33) / 3, with tr s = (w11 + w22 + w33) / (3 lambda + 2 mu).
@@ -762,10 +719,8 @@ hipError_t launch_dot(const T *a, const T *b, long long n, double *partial, doub
                                            unsigned long long *, hipStream_t);                                       \
     template hipError_t launch_inject<T>(const Dev<T> &, const T *, hipStream_t);                                    \
     template hipError_t launch_gather<T>(const Dev<T> &, const Rec &, double *, hipStream_t);                        \
-    template hipError_t launch_scatter<T>(const Dev<T> &, const Rec &, const double *, hipStream_t);                 \
+    template hipError_t launch_scatter<T>(const Dev<T> &, const Rec &, const double *, hipStream_t, const int *);    \
     template hipError_t launch_extract<T>(const Dev<T> &, T *, hipStream_t);                                         \
-    template hipError_t launch_gather_ctr<T>(const Dev<T> &, const Rec &, double *, int *, hipStream_t);             \
-    template hipError_t launch_scatter_ctr<T>(const Dev<T> &, const Rec &, const double *, int *, hipStream_t);                                         \
     template hipError_t launch_dot<T>(const T *, const T *, long long, double *, double *, hipStream_t);           \
     template hipError_t launch_relax_setup<T>(const Dev<T> &, const Tiles &, const float *, const Relax<T> &,      \
                                               hipStream_t);                                                        \

@@ -365,14 +365,19 @@ __device__ __forceinline__ double block_sum(double v) {
 // epart[blockIdx.x * NT + threadIdx.x], once on every path, padding blocks and lanes outside
 // the grid included (a block reduction would need every lane at a barrier, and the early exits
 // of the plain pass are kept as they are).
+//
+// ctr (captured step graphs, el_exec): a device step counter.  The forward's gather blocks
+// write trace row *ctr of the traces at grow (the stress pass that follows advances it); the
+// adjoint pass steps it back by one, for the scatter that follows.
 template <typename T, bool ADJ, bool EN>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 5 : 1))) void k_vel(
-    Dev<T> d, Tiles tl, Rec r, double *grow, double *epart) {
+    Dev<T> d, Tiles tl, Rec r, double *grow, double *epart, int *ctr) {
     static_assert(NT == 256, "gather_block works on blocks of 256 threads");
     static_assert(!(ADJ && EN), "the energy belongs to the forward recursion");
+    if (ADJ && ctr && blockIdx.x == 0 && threadIdx.x == 0) *ctr -= 1;
     if (!ADJ && grow && (int)blockIdx.x >= 8 * tl.per) {
         // the trace row of the stresses this pass reads (the previous step's), see launch_velocity
-        gather_block(d, r, grow, (int)blockIdx.x - 8 * tl.per);
+        gather_block(d, r, ctr ? grow + (size_t)(*ctr) * r.nrec : grow, (int)blockIdx.x - 8 * tl.per);
         return;
     }
     int x0, y0, z0, z1, t = 0, edges = 0;
@@ -674,8 +679,12 @@ __device__ __forceinline__ void fluid_str(const Dev<T> &d, int i, int j, int y0,
     }
 }
 
+// ctr (captured step graphs): the forward pass advances the device step counter its velocity
+// pass's gather blocks read (all of that launch has completed).
 template <typename T, bool ADJ>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 5 : 1))) void k_str(Dev<T> d, Tiles tl) {
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 5 : 1))) void k_str(Dev<T> d, Tiles tl,
+                                                                                                   int *ctr) {
+    if (!ADJ && ctr && blockIdx.x == 0 && threadIdx.x == 0) *ctr += 1;
     int x0, y0, z0, z1, t = 0, edges = 0;
     bool fast = false, uni = false, cols = false;
     if (!tile_of(tl, d.nz, x0, y0, z0, z1, t, fast, uni, cols, edges)) return;
@@ -856,31 +865,31 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
 
 template <typename T>
 hipError_t launch_velocity(const Dev<T> &d, const Tiles &tl, hipStream_t s, const Rec *r, double *grow,
-                           double *epart) {
+                           double *epart, int *ctr) {
     const bool g = r && grow && r->nrec > 0;
     const int blocks = 8 * tl.per + (g ? gather_blocks(r->nrec) : 0);
     if (epart)
         hipLaunchKernelGGL((k_vel<T, false, true>), dim3(blocks), dim3(NT), 0, s, d, tl, g ? *r : Rec{},
-                           g ? grow : nullptr, epart);
+                           g ? grow : nullptr, epart, ctr);
     else
         hipLaunchKernelGGL((k_vel<T, false, false>), dim3(blocks), dim3(NT), 0, s, d, tl, g ? *r : Rec{},
-                           g ? grow : nullptr, (double *)nullptr);
+                           g ? grow : nullptr, (double *)nullptr, ctr);
     return hipGetLastError();
 }
 template <typename T>
-hipError_t launch_stress(const Dev<T> &d, const Tiles &tl, hipStream_t s) {
-    hipLaunchKernelGGL((k_str<T, false>), dim3(8 * tl.per), dim3(NT), 0, s, d, tl);
+hipError_t launch_stress(const Dev<T> &d, const Tiles &tl, hipStream_t s, int *ctr) {
+    hipLaunchKernelGGL((k_str<T, false>), dim3(8 * tl.per), dim3(NT), 0, s, d, tl, ctr);
     return hipGetLastError();
 }
 template <typename T>
-hipError_t launch_adj_velocity(const Dev<T> &d, const Tiles &tl, hipStream_t s) {
+hipError_t launch_adj_velocity(const Dev<T> &d, const Tiles &tl, hipStream_t s, int *ctr) {
     hipLaunchKernelGGL((k_vel<T, true, false>), dim3(8 * tl.per), dim3(NT), 0, s, d, tl, Rec{}, (double *)nullptr,
-                       (double *)nullptr);
+                       (double *)nullptr, ctr);
     return hipGetLastError();
 }
 template <typename T>
 hipError_t launch_adj_stress(const Dev<T> &d, const Tiles &tl, hipStream_t s) {
-    hipLaunchKernelGGL((k_str<T, true>), dim3(8 * tl.per), dim3(NT), 0, s, d, tl);
+    hipLaunchKernelGGL((k_str<T, true>), dim3(8 * tl.per), dim3(NT), 0, s, d, tl, (int *)nullptr);
     return hipGetLastError();
 }
 
@@ -994,10 +1003,10 @@ hipError_t launch_fluid_fill(const Dev<T> &d, const Tiles &tl, hipStream_t s) {
 #define EL_STENCIL_INST(T)                                                                  \
     template hipError_t launch_fluid_fill<T>(const Dev<T> &, const Tiles &, hipStream_t);   \
     template hipError_t launch_velocity<T>(const Dev<T> &, const Tiles &, hipStream_t, const Rec *, double *,  \
-                                           double *);                                                          \
+                                           double *, int *);                                                   \
     template hipError_t launch_energy_pot<T>(const Dev<T> &, const Tiles &, double *, hipStream_t);            \
-    template hipError_t launch_stress<T>(const Dev<T> &, const Tiles &, hipStream_t);       \
-    template hipError_t launch_adj_velocity<T>(const Dev<T> &, const Tiles &, hipStream_t); \
+    template hipError_t launch_stress<T>(const Dev<T> &, const Tiles &, hipStream_t, int *);       \
+    template hipError_t launch_adj_velocity<T>(const Dev<T> &, const Tiles &, hipStream_t, int *); \
     template hipError_t launch_adj_stress<T>(const Dev<T> &, const Tiles &, hipStream_t);
 
 EL_STENCIL_INST(float)

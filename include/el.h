@@ -59,7 +59,7 @@ typedef int32_t el_status;
 #define EL_ERANGE    -3   /* a receiver outside [0, n-1]*dx on some axis                    */
 #define EL_ENOMEM    -4   /* workspace smaller than el_plan_bytes() says                    */
 #define EL_EDEVICE   -5   /* a HIP runtime call failed                                      */
-#define EL_EBUSY     -6   /* every executor slot is running an operation                    */
+#define EL_EBUSY     -6   /* every executor or group slot is in use                         */
 
 #define EL_F32 0          /* fields, stencils, p0 and p_adj in float  */
 #define EL_F64 1          /* fields, stencils, p0 and p_adj in double */
@@ -348,8 +348,10 @@ el_status el_plan_fluid_path(el_plan plan, int32_t enable, el_fluid_stats *stats
 #define EL_K_STRESS       1   /* forward stress pass (+ psi slabs)             */
 #define EL_K_ADJ_VELOCITY 2   /* adjoint pass producing the velocity adjoint   */
 #define EL_K_ADJ_STRESS   3   /* adjoint pass producing the stress adjoint     */
+                              /* (it also scatters the next trace row)         */
 #define EL_K_GATHER       4   /* receiver gather of the last trace row         */
-#define EL_K_SCATTER      5   /* receiver scatter (adjoint)                    */
+#define EL_K_SCATTER      5   /* receiver scatter of the last trace row        */
+                              /* (adjoint; the first thing H^T does)           */
 #define EL_K_RELAX        6   /* relaxation sub-update (forward) or its        */
                               /* transpose (adjoint), plans with nmech > 0     */
 #define EL_K_COUNT        7
@@ -411,6 +413,75 @@ el_status el_exec_wait(el_exec ex, int32_t slot);
 
 /* Number of slots and how many are running an operation. */
 el_status el_exec_slots(el_exec ex, int32_t *total, int32_t *busy);
+
+/*
+ * Group: grouped time stepping of many operations (serving).
+ *
+ * A group holds up to `max_members` operations of one precision, each on its
+ * own plan (grids, media, step counts and receivers may differ).  el_group_run
+ * advances every running member by one time step per tick, the same step as
+ * el_forward / el_adjoint take (Sec. 2.2 for H, its transpose for H^T): one
+ * velocity launch and one stress launch (which, for adjoint members, also adds
+ * Theta^T of the trace row) serve up to four members at once, their tiles side
+ * by side in one grid, so that small grids share the device.  Members join (el_group_add) and leave (after their
+ * last step, or el_group_remove) between ticks; nothing is captured, the
+ * launch arguments are rebuilt each tick.  A member's result is bitwise that
+ * of el_forward / el_adjoint on its plan.
+ *
+ * All work runs on the group's own stream (default priority) and returns at
+ * once.  A member's plan must not be used elsewhere, nor its buffers
+ * released, before el_group_poll reports it done.  Calls on one group must not
+ * overlap (one host thread at a time).
+ */
+typedef struct el_group_ *el_group;
+
+/* Create a group on the current device.  max_members in 1..64; precision
+ * EL_F32 or EL_F64 (every member's plan must have it).  EL_EDEVICE if the
+ * stream or events cannot be created. */
+el_status el_group_create(el_group *out, int32_t max_members, int32_t precision);
+
+/* Wait for the group's stream, then release the group (members' buffers are
+ * the caller's). */
+el_status el_group_destroy(el_group g);
+
+/*
+ * Add `op` on `plan` as a member; *slot receives its index.  Enqueues the
+ * initial state (Sec. 2.2: zero fields, then p0 injected through tau' for the
+ * forward, Theta^T of the last trace row for the adjoint) after all work
+ * enqueued so far on `stream` (the caller's stream that writes `in`; NULL =
+ * the null stream) and after the plan's previous operation.  in/out as for
+ * el_exec_start.  A plan with nsteps = 1 finishes here.  EL_EBUSY if every
+ * slot is used; EL_EINVAL for a bad op, NULL buffers, a plan of another
+ * precision or device, or a plan that is already a member.
+ */
+el_status el_group_add(el_group g, el_plan plan, int32_t op, const void *in, void *out, void *stream,
+                       int32_t *slot);
+
+/*
+ * Enqueue `ticks` time steps of every running member (fewer if all members
+ * finish).  A member that takes its last step also gets its final work
+ * (last trace row, or the extraction p_adj = tau'^T v_0) and completes.
+ * Each call records an event that el_group_sync waits for.
+ */
+el_status el_group_run(el_group g, int32_t ticks);
+
+/* Block until at most `pending` of the el_group_run calls so far are still
+ * running on the device (pending = 0: all done).  Bounds how far the host
+ * runs ahead of the device, and releases the calls' events. */
+el_status el_group_sync(el_group g, int32_t pending);
+
+/* Non-blocking: *steps_done = steps enqueued for the slot's member so far;
+ * *done = 1 once its operation (or its withdrawal) has completed on the
+ * device, and the slot is then free.  Either pointer may be NULL. */
+el_status el_group_poll(el_group g, int32_t slot, int32_t *steps_done, int32_t *done);
+
+/* Withdraw the slot's member: it takes no further steps and its output is
+ * left incomplete; the slot frees once the work already enqueued for it has
+ * completed (el_group_poll). */
+el_status el_group_remove(el_group g, int32_t slot);
+
+/* Number of slots, slots in use, and members still taking steps. */
+el_status el_group_members(el_group g, int32_t *total, int32_t *used, int32_t *running);
 
 #ifdef __cplusplus
 }

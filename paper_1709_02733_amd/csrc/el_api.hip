@@ -98,6 +98,9 @@ bool layout(const el_grid &g, int nrec, Layout *L) {
     L->counter = take(256);
     {
         const Tiles t = make_tiles(g.nx, g.ny, g.nz);
+        L->csr_tslot = take((size_t)t.ntiles * 4);
+        L->csr_loff = take(std::min((size_t)t.ntiles, E) * (kTileX * kTileY + 1) * 4);
+        L->csr_tpts = take(E * 4);
         L->tile_order = take((size_t)8 * t.per * sizeof(int));
         L->tile_flags = take(2 * (size_t)t.ntiles);
         L->tile_media = take((size_t)4 * t.ntiles * es);
@@ -434,6 +437,33 @@ el_status upload_receivers(el_plan_ *p, const double *rec, hipStream_t s) {
         ew.push_back(w[o]);
     }
     row.push_back((int)order.size());
+    // the points of each stencil tile and column (the adjoint stress launch adds Theta^T y at
+    // the cells its lanes own): sorted by (tile, column key), a slot per tile with points
+    const Tiles &tt = p->tiles;
+    constexpr int kKeys = kTileX * kTileY;
+    std::vector<long long> tkey(pt.size());
+    std::vector<int> tpts(pt.size()), tslot(tt.ntiles, -1), loff;
+    for (size_t q = 0; q < pt.size(); ++q) {
+        const int i = ptc[3 * q], j = ptc[3 * q + 1], k = ptc[3 * q + 2];
+        const long long t = ((long long)(k / tt.zc) * tt.nty + j / kTileY) * tt.ntx + i / kTileX;
+        tkey[q] = t * kKeys + (i % kTileX) + kTileX * (j % kTileY);
+        tpts[q] = (int)q;
+    }
+    std::stable_sort(tpts.begin(), tpts.end(), [&](int a, int b) { return tkey[a] < tkey[b]; });
+    for (size_t e = 0; e < tpts.size();) {
+        const int t = (int)(tkey[tpts[e]] / kKeys);
+        const int slot = (int)(loff.size() / (kKeys + 1));
+        tslot[t] = slot;
+        loff.resize(loff.size() + kKeys + 1);
+        int *lo = loff.data() + (size_t)slot * (kKeys + 1);
+        size_t f = e;
+        for (int key = 0; key <= kKeys; ++key) {
+            while (f < tpts.size() && tkey[tpts[f]] < (long long)t * kKeys + key) ++f;
+            lo[key] = (int)f;
+        }
+        while (f < tpts.size() && tkey[tpts[f]] / kKeys == t) ++f;
+        e = f;
+    }
     char *ws = p->ws;
     Rec &r = p->rec;
     r.nrec = L;
@@ -446,7 +476,16 @@ el_status upload_receivers(el_plan_ *p, const double *rec, hipStream_t s) {
     r.row = reinterpret_cast<int *>(ws + p->L.csr_row);
     r.ent_rec = reinterpret_cast<int *>(ws + p->L.csr_rec);
     r.ent_w = reinterpret_cast<double *>(ws + p->L.csr_w);
+    r.tslot = reinterpret_cast<int *>(ws + p->L.csr_tslot);
+    r.loff = reinterpret_cast<int *>(ws + p->L.csr_loff);
+    r.tpts = reinterpret_cast<int *>(ws + p->L.csr_tpts);
+    HIP_TRY(hipMemcpyAsync((void *)r.tslot, tslot.data(), tslot.size() * 4, hipMemcpyHostToDevice, s),
+            "copy receivers");
     if (L > 0) {
+        HIP_TRY(hipMemcpyAsync((void *)r.loff, loff.data(), loff.size() * 4, hipMemcpyHostToDevice, s),
+                "copy receivers");
+        HIP_TRY(hipMemcpyAsync((void *)r.tpts, tpts.data(), tpts.size() * 4, hipMemcpyHostToDevice, s),
+                "copy receivers");
         HIP_TRY(hipMemcpyAsync((void *)r.idx, idx.data(), idx.size() * 8, hipMemcpyHostToDevice, s), "copy receivers");
         HIP_TRY(hipMemcpyAsync((void *)r.w, w.data(), w.size() * 8, hipMemcpyHostToDevice, s), "copy receivers");
         HIP_TRY(hipMemcpyAsync((void *)r.pt, pt.data(), pt.size() * 8, hipMemcpyHostToDevice, s), "copy receivers");
@@ -455,8 +494,8 @@ el_status upload_receivers(el_plan_ *p, const double *rec, hipStream_t s) {
         HIP_TRY(hipMemcpyAsync((void *)r.ent_rec, erec.data(), erec.size() * 4, hipMemcpyHostToDevice, s),
                 "copy receivers");
         HIP_TRY(hipMemcpyAsync((void *)r.ent_w, ew.data(), ew.size() * 8, hipMemcpyHostToDevice, s), "copy receivers");
-        HIP_TRY(hipStreamSynchronize(s), "receiver upload");
     }
+    HIP_TRY(hipStreamSynchronize(s), "receiver upload");
     return EL_OK;
 }
 
@@ -555,9 +594,10 @@ el_status run_adjoint(el_plan p, Dev<T> &d, const double *y, T *out, hipStream_t
         // the step (the forward applies R between its velocity and stress updates)
         if (rx.L > 0)
             HIP_TRY(timed(p, EL_K_RELAX, m, s, [&] { return launch_relax(d, p->tiles, rx, true, s); }), "relaxation");
-        HIP_TRY(timed(p, EL_K_ADJ_STRESS, m, s, [&] { return launch_adj_stress(d, p->tiles, s); }), "adjoint stress pass");
-        HIP_TRY(timed(p, EL_K_SCATTER, m - 1, s, [&] { return launch_scatter(d, p->rec, y + (size_t)(m - 1) * L, s); }),
-                "scatter");
+        // the adjoint stress launch also adds Theta^T y of row m-1 (launch_adj_stress)
+        HIP_TRY(timed(p, EL_K_ADJ_STRESS, m, s,
+                      [&] { return launch_adj_stress(d, p->tiles, s, &p->rec, y + (size_t)(m - 1) * L); }),
+                "adjoint stress pass");
     }
     if (p->fluid_path && p->fast_tiles > 0) HIP_TRY(launch_fluid_fill(d, p->tiles, s), "fluid fill");
     HIP_TRY(launch_extract(d, out, s), "extract");

@@ -48,8 +48,8 @@ el_status hipf(hipError_t e, const char *what) {
 
 // One time step with the trace row taken from the device counter: the forward velocity pass
 // gathers row *ctr (the stresses of the previous step) in extra blocks and the stress pass
-// advances the counter; the adjoint velocity pass steps it back and the scatter after the
-// adjoint stress pass reads that row.
+// advances the counter; the adjoint velocity pass steps it back and the adjoint stress pass
+// adds Theta^T y of that row.
 template <typename T>
 hipError_t launch_step(el_plan p, const Dev<T> &d, int op, void *traces, int *ctr, hipStream_t s) {
     hipError_t e;
@@ -61,8 +61,7 @@ hipError_t launch_step(el_plan p, const Dev<T> &d, int op, void *traces, int *ct
     } else {
         e = launch_adj_velocity(d, p->tiles, s, ctr);
         if (e == hipSuccess) e = launch_relax(d, p->tiles, rx, true, s);
-        if (e == hipSuccess) e = launch_adj_stress(d, p->tiles, s);
-        if (e == hipSuccess) e = launch_scatter(d, p->rec, static_cast<const double *>(traces), s, ctr);
+        if (e == hipSuccess) e = launch_adj_stress(d, p->tiles, s, &p->rec, static_cast<const double *>(traces), ctr);
     }
     return e;
 }

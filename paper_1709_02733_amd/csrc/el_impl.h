@@ -174,6 +174,12 @@ struct Rec {
     const int *row;          // [npts + 1] offsets into ent_rec / ent_w
     const int *ent_rec;      // receiver of each entry
     const double *ent_w;     // weight of each entry
+    // scatter points by stencil tile and column: tslot[t] is -1 for a tile without points,
+    // else s, and the points of column (c, r) of the tile (key c + kTileX r) are
+    // tpts[loff[s (kTileX kTileY + 1) + key] .. loff[... + key + 1])
+    const int *tslot;        // [ntiles]
+    const int *loff;         // [slots][kTileX kTileY + 1]
+    const int *tpts;         // [npts] point numbers sorted by (tile, key)
 };
 
 // Receiver gather: p_hat_m[l] = -sum_c w_lc (s11 + s22 + s33)[c]  (Sec. 3, eq. interpgrid), in
@@ -202,13 +208,64 @@ __device__ __forceinline__ void gather_block(const Dev<T> &d, const Rec &r, doub
 }
 inline int gather_blocks(int nrec) { return ((nrec + 7) / 8 + 3) / 4; }
 
+// s_kk += Theta^T y_m at point t of the grid-point-major table (entries summed in a fixed
+// order).  With the adjoint stress kept as w = C s this adds (3 lambda + 2 mu) delta to w11,
+// w22, w33, and the normal adjoint memory variables, which hold a (b psi~ + dt w) for the
+// coming step, receive a dt times the same increment.
+template <typename T>
+__device__ __forceinline__ void scatter_point(const Dev<T> &d, const Rec &r, const double *y, int t) {
+    double acc = 0.0;
+    for (int e = r.row[t]; e < r.row[t + 1]; ++e) acc += r.ent_w[e] * y[r.ent_rec[e]];
+    const long long q = r.pt[t];
+    const T dw = T(-acc) * (T(3) * d.lam[q] + T(2) * d.mu[q]);
+    d.f[S11][q] += dw;
+    d.f[S22][q] += dw;
+    d.f[S33][q] += dw;
+    if (d.P > 0) {
+        const int crd[3] = {r.ptc[3 * t], r.ptc[3 * t + 1], r.ptc[3 * t + 2]};
+        for (int a = 0; a < 3; ++a) {
+            const int s = slab_own(crd[a], d.P, d.hi[a]);
+            if (s < 0) continue;
+            const T inc = d.pa[a][0][crd[a]] * d.dt * dw;
+            T *g = d.mem[a][3 + a];
+            g[slab_byte(d, a, s, crd[0], crd[1], crd[2]) / sizeof(T)] += inc;
+            const int tw = slab_twin(crd[a], d.P, d.hi[a]);
+            if (tw >= 0) g[slab_byte(d, a, tw, crd[0], crd[1], crd[2]) / sizeof(T)] += inc;
+        }
+    }
+}
+
+// Arguments of a stencil launch over the tiles of G plans of one precision (G = 1: a plan's
+// own passes; G = kGroupMax: the grouped passes of el_group).  Member q owns blocks
+// first[q] .. first[q+1]-1; each first[q] is a multiple of 8, so that the member's block
+// b - first[q] runs on XCD (b - first[q]) % 8 as its tile order assumes.  Entries past the
+// last member repeat the total block count.  row[q]: the trace row that member's gather
+// blocks write (forward velocity launch) or its scatter reads (grouped scatter), or null.
+constexpr int kGroupMax = 4;
+template <typename T, int G>
+struct Grp {
+    Dev<T> d[G];
+    Tiles tl[G];
+    Rec r[G];
+    double *row[G];
+    int first[G + 1];
+    int n;
+};
+template <typename T, int G>
+__device__ __forceinline__ int member_of(const Grp<T, G> &g) {
+    int q = 0;
+#pragma unroll
+    for (int k = 1; k < G; ++k) q += (int)blockIdx.x >= g.first[k] ? 1 : 0;
+    return q;
+}
+
 // Workspace layout (byte offsets), computed identically for sizing and binding.
 struct Layout {
     size_t field[NFIELD];
     size_t map[4];           // lam, mu, rho, alpha
     size_t mem[3][6];
     size_t pa[3][2], pb[3][2];
-    size_t rec_idx, rec_w, rec_fl, csr_pt, csr_ptc, csr_row, csr_rec, csr_w;
+    size_t rec_idx, rec_w, rec_fl, csr_pt, csr_ptc, csr_row, csr_rec, csr_w, csr_tslot, csr_loff, csr_tpts;
     size_t stats;            // media statistics (16 doubles)
     size_t counter;          // device step counter of captured step graphs
     size_t tile_order;       // tile of each stencil block
@@ -260,9 +317,19 @@ template <typename T> hipError_t launch_stress(const Dev<T> &d, const Tiles &tl,
 template <typename T> hipError_t launch_gather(const Dev<T> &d, const Rec &r, double *trace_row, hipStream_t s);
 template <typename T> hipError_t launch_adj_velocity(const Dev<T> &d, const Tiles &tl, hipStream_t s,
                                                      int *ctr = nullptr);
-template <typename T> hipError_t launch_adj_stress(const Dev<T> &d, const Tiles &tl, hipStream_t s);
+// The adjoint stress launch also applies the scatter of trace row y (r and y non-null): each
+// lane, after its column's update, adds Theta^T y at the scatter points of its own cells (the
+// values it has just written), in the order and arithmetic of launch_scatter.  ctr != null:
+// y is the whole trace array and the row is *ctr (stepped back by the adjoint velocity launch).
+template <typename T> hipError_t launch_adj_stress(const Dev<T> &d, const Tiles &tl, hipStream_t s,
+                                                   const Rec *r = nullptr, const double *y = nullptr,
+                                                   int *ctr = nullptr);
 template <typename T> hipError_t launch_scatter(const Dev<T> &d, const Rec &r, const double *y, hipStream_t s,
                                                 const int *ctr = nullptr);
+// Grouped passes (el_group): pass 0 velocity (with the gather blocks of members whose row is
+// set), 1 stress, 2 adjoint velocity, 3 adjoint stress (with the scatter of members whose row
+// is set); g.first from the members' 8 * per blocks (plus gather blocks for pass 0).
+template <typename T> hipError_t launch_group_pass(const Grp<T, kGroupMax> &g, int pass, hipStream_t s);
 template <typename T> hipError_t launch_extract(const Dev<T> &d, T *p, hipStream_t s);
 template <typename T> hipError_t launch_fluid_fill(const Dev<T> &d, const Tiles &tl, hipStream_t s);
 hipError_t launch_eir(const double *h, int nh, const double *in, double *out, int M, int L, int transpose,

@@ -324,9 +324,6 @@ hipError_t launch_gather(const Dev<T> &d, const Rec &r, double *row, hipStream_t
     return hipGetLastError();
 }
 
-template <typename T>
-__device__ __forceinline__ void scatter_point(const Dev<T> &d, const Rec &r, const double *y, int t);
-
 // ctr != null (captured step graphs): y is the whole trace array and the row is *ctr (the
 // adjoint velocity launch before it has stepped the counter back), so one graph of K steps
 // serves every chunk of the time loop.
@@ -351,33 +348,6 @@ __global__ void k_set_counter(int *ctr, int v) {
 hipError_t launch_set_counter(int *ctr, int v, hipStream_t s) {
     hipLaunchKernelGGL(k_set_counter, dim3(1), dim3(64), 0, s, ctr, v);
     return hipGetLastError();
-}
-
-// s_kk += Theta^T y_m at point t of the grid-point-major table (entries summed in a fixed
-// order).  With the adjoint stress kept as w = C s this adds (3 lambda + 2 mu) delta to w11,
-// w22, w33, and the normal adjoint memory variables, which hold a (b psi~ + dt w) for the
-// coming step, receive a dt times the same increment.
-template <typename T>
-__device__ __forceinline__ void scatter_point(const Dev<T> &d, const Rec &r, const double *y, int t) {
-    double acc = 0.0;
-    for (int e = r.row[t]; e < r.row[t + 1]; ++e) acc += r.ent_w[e] * y[r.ent_rec[e]];
-    const long long q = r.pt[t];
-    const T dw = T(-acc) * (T(3) * d.lam[q] + T(2) * d.mu[q]);
-    d.f[S11][q] += dw;
-    d.f[S22][q] += dw;
-    d.f[S33][q] += dw;
-    if (d.P > 0) {
-        const int crd[3] = {r.ptc[3 * t], r.ptc[3 * t + 1], r.ptc[3 * t + 2]};
-        for (int a = 0; a < 3; ++a) {
-            const int s = slab_own(crd[a], d.P, d.hi[a]);
-            if (s < 0) continue;
-            const T inc = d.pa[a][0][crd[a]] * d.dt * dw;
-            T *g = d.mem[a][3 + a];
-            g[slab_byte(d, a, s, crd[0], crd[1], crd[2]) / sizeof(T)] += inc;
-            const int tw = slab_twin(crd[a], d.P, d.hi[a]);
-            if (tw >= 0) g[slab_byte(d, a, tw, crd[0], crd[1], crd[2]) / sizeof(T)] += inc;
-        }
-    }
 }
 
 // p_adj = tau'^T v_0 = -(s11 + s22 + s33) / 3, with tr s = (w11 + w22 + w33) / (3 lambda + 2 mu).

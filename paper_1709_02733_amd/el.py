@@ -59,7 +59,9 @@ EXPORTS = ("el_version", "el_status_string", "el_last_error", "el_grid_check", "
            "el_plan_field", "el_plan_layout", "el_plan_sizes", "el_plan_relaxation", "el_plan_fluid_path",
            "el_plan_timing",
            "el_plan_kernel_time",
-           "el_exec_create", "el_exec_destroy", "el_exec_start", "el_exec_poll", "el_exec_wait", "el_exec_slots")
+           "el_exec_create", "el_exec_destroy", "el_exec_start", "el_exec_poll", "el_exec_wait", "el_exec_slots",
+           "el_group_create", "el_group_destroy", "el_group_add", "el_group_run", "el_group_sync", "el_group_poll",
+           "el_group_remove", "el_group_members")
 KERNELS = ("velocity", "stress", "adj_velocity", "adj_stress", "gather", "scatter", "relax")
 
 
@@ -124,6 +126,22 @@ def lib():
         L.el_exec_wait.argtypes = [vp, i32]
         L.el_exec_slots.restype = st
         L.el_exec_slots.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
+        L.el_group_create.restype = st
+        L.el_group_create.argtypes = [ctypes.POINTER(vp), i32, i32]
+        L.el_group_destroy.restype = st
+        L.el_group_destroy.argtypes = [vp]
+        L.el_group_add.restype = st
+        L.el_group_add.argtypes = [vp, vp, i32, vp, vp, vp, ctypes.POINTER(i32)]
+        L.el_group_run.restype = st
+        L.el_group_run.argtypes = [vp, i32]
+        L.el_group_sync.restype = st
+        L.el_group_sync.argtypes = [vp, i32]
+        L.el_group_poll.restype = st
+        L.el_group_poll.argtypes = [vp, i32, ctypes.POINTER(i32), ctypes.POINTER(i32)]
+        L.el_group_remove.restype = st
+        L.el_group_remove.argtypes = [vp, i32]
+        L.el_group_members.restype = st
+        L.el_group_members.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)]
         _lib = L
     return _lib
 
@@ -442,8 +460,81 @@ class Executor:
     def close(self):
         h = getattr(self, "_h", None)
         if h is not None and h.value:
-            with torch.cuda.device(self.device):
-                self._lib.el_exec_destroy(h)   # the library handle outlives module teardown
+            if torch is not None and torch.cuda is not None:
+                with torch.cuda.device(self.device):
+                    self._lib.el_exec_destroy(h)   # the library handle outlives module teardown
+            else:
+                self._lib.el_exec_destroy(h)
+        self._h = None
+        self._held = {}
+
+    __del__ = close
+
+
+class Group:
+    """Grouped time stepping of many operator applications (el_group).
+
+    add() makes a forward or adjoint application of a plan a member; run(ticks)
+    advances every running member by `ticks` time steps, up to four members per
+    launch; poll() reports a member's completion; remove() withdraws one.  The
+    plans and in/out tensors are kept alive here until their member is done.
+    """
+
+    def __init__(self, max_members: int = 8, precision: int = EL_F32, device=None):
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        h = ctypes.c_void_p(None)
+        with torch.cuda.device(self.device):
+            _check(lib().el_group_create(ctypes.byref(h), int(max_members), int(precision)))
+        self._h = h
+        self._lib = lib()
+        self.max_members = int(max_members)
+        self._held = {}
+
+    def add(self, plan: "Plan", op: int, inp: torch.Tensor, out: torch.Tensor, stream=None) -> int:
+        """The member starts after the work enqueued so far on `stream` (default: the current
+        torch stream, which wrote inp)."""
+        slot = ctypes.c_int32(-1)
+        with torch.cuda.device(self.device):
+            _check(lib().el_group_add(self._h, plan._h, int(op), ctypes.c_void_p(inp.data_ptr()),
+                                      ctypes.c_void_p(out.data_ptr()), _stream(stream), ctypes.byref(slot)))
+        self._held[slot.value] = (plan, inp, out)
+        return slot.value
+
+    def run(self, ticks: int):
+        with torch.cuda.device(self.device):
+            _check(lib().el_group_run(self._h, int(ticks)))
+
+    def sync(self, pending: int = 0):
+        with torch.cuda.device(self.device):
+            _check(lib().el_group_sync(self._h, int(pending)))
+
+    def poll(self, slot: int):
+        """(steps enqueued, done)."""
+        steps, done = ctypes.c_int32(0), ctypes.c_int32(0)
+        with torch.cuda.device(self.device):
+            _check(lib().el_group_poll(self._h, int(slot), ctypes.byref(steps), ctypes.byref(done)))
+        if done.value:
+            self._held.pop(slot, None)
+        return steps.value, bool(done.value)
+
+    def remove(self, slot: int):
+        with torch.cuda.device(self.device):
+            _check(lib().el_group_remove(self._h, int(slot)))
+
+    def members(self):
+        """(slots, slots in use, members still stepping)."""
+        t, u, r = ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_int32(0)
+        _check(lib().el_group_members(self._h, ctypes.byref(t), ctypes.byref(u), ctypes.byref(r)))
+        return t.value, u.value, r.value
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            if torch is not None and torch.cuda is not None:
+                with torch.cuda.device(self.device):
+                    self._lib.el_group_destroy(h)
+            else:
+                self._lib.el_group_destroy(h)
         self._h = None
         self._held = {}
 

@@ -6,15 +6,18 @@ them:
 
 * plain: first come, first served, one request at a time, each through
   el_forward / el_adjoint with per-step kernel launches.
-* batched (continuous batching): a request is admitted as soon as it has
-  arrived, an executor slot is free and the HBM budget (sum of the plans'
-  workspaces and buffers of the admitted requests) allows it.  Each admitted
-  request runs on its own slot stream as replays of captured step graphs,
-  concurrently with the others; the host builds the next plans while the
-  device works and retires requests as their completion events fire.
+* grouped (continuous batching, el_group): a request is admitted as soon as
+  it has arrived, a group slot is free and the HBM budget (sum of the plans'
+  workspaces and buffers of the admitted requests) allows it.  A worker
+  thread builds its plan while the device works; it then joins the group,
+  which advances all running requests one time step per tick with one
+  launch per sub-update for up to four requests at a time.  Requests leave
+  the group after their last step.
+* executor (run_batched): each admitted request runs on its own slot stream
+  as replays of captured step graphs, concurrently with the others.
 
-Both paths run the same kernels in the same order per request, so each
-result is bitwise the same alone and in the mix.  The report gives
+All paths run the same per-cell arithmetic in the same order per request, so
+each result is bitwise the same alone and in the mix.  The report gives
 throughput (requests/s and Gcell-updates/s) and p50/p99 latency (arrival to
 result) per arrival rate.
 
@@ -24,6 +27,7 @@ from __future__ import annotations
 
 import argparse
 import collections
+import concurrent.futures
 import dataclasses
 import json
 import math
@@ -82,14 +86,19 @@ def clone_requests(reqs):
 class Workloads:
     """Device-resident inputs per grid size: one skull-recipe medium per size, its vessel
     p0, and receivers on the upper hemisphere of radius 0.47 n (the recipe of the 384^3
-    workload, scaled)."""
+    workload, scaled).
 
-    def __init__(self, sizes=SIZES, device=None, seed=7, keep_outputs=False):
+    per_request_media: each request gets its own medium, the size's skull medium shifted
+    by up to 4 cells along each axis and its sound speeds and density scaled by up to
+    +-3% (seeded by the request), so that every plan is built from different maps."""
+
+    def __init__(self, sizes=SIZES, device=None, seed=7, keep_outputs=False, per_request_media=False):
         import torch
         from . import el
         self.torch, self.el = torch, el
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
         self.keep_outputs = keep_outputs
+        self.per_request_media = per_request_media
         self.media = {}
         for n in sizes:
             sc = S.skull_scenario(n=n, seed=seed + n, nsteps=S.serving_steps(n), npml=16, nrec=8)
@@ -112,11 +121,31 @@ class Workloads:
         io = r.n ** 3 * 4 + r.nsteps * r.nrec * 8
         return int(ws + io)
 
-    def plan(self, r: Request):
+    def medium(self, r: Request):
+        """lam, mu, rho, alpha of the request (device tensors)."""
         m = self.media[r.n]
-        sc = m["sc"]
-        return self.el.Plan(r.n, r.n, r.n, sc.dx, sc.dt, r.nsteps, 16, m["lam"], m["mu"], m["rho"], m["alpha"],
-                            self.receivers(r), device=self.device)
+        if not self.per_request_media:
+            return m["lam"], m["mu"], m["rho"], m["alpha"]
+        torch = self.torch
+        rng = np.random.default_rng(r.seed)
+        shift = tuple(int(v) for v in rng.integers(-4, 5, size=3))
+        cs, rs = 1.0 + rng.uniform(-0.03, 0.03, size=2)
+        roll = lambda a: torch.roll(a, shifts=shift, dims=(0, 1, 2))
+        # lambda and mu scale with rho c^2: sound speeds by cs, density by rs
+        k = float(rs * cs * cs)
+        return roll(m["lam"]) * k, roll(m["mu"]) * k, roll(m["rho"]) * float(rs), roll(m["alpha"])
+
+    def plan(self, r: Request):
+        sc = self.media[r.n]["sc"]
+        lam, mu, rho, alpha = self.medium(r)
+        # a medium whose sound speeds grew by up to 3% needs a time step to match (CFL)
+        dt = sc.dt / 1.03 if self.per_request_media else sc.dt
+        return self.el.Plan(r.n, r.n, r.n, sc.dx, dt, r.nsteps, 16, lam, mu, rho, alpha, self.receivers(r),
+                            device=self.device)
+
+    def settle(self):
+        """Wait for the work this thread enqueued (a plan's inputs built off the main thread)."""
+        self.torch.cuda.current_stream(self.device).synchronize()
 
     def io(self, r: Request):
         torch = self.torch
@@ -230,6 +259,118 @@ def run_batched(reqs, wl, executor, budget_bytes: float = 200e9, clock=time.perf
     return reqs
 
 
+def _cells(r: Request) -> int:
+    return r.n ** 3
+
+
+def run_grouped(reqs, wl, group, budget_bytes: float = 200e9, clock=time.perf_counter, sleep=time.sleep,
+                trace=None, run_ms: float = 2.0, rate_guess: float = 40e9, pool=None):
+    """Continuous batching over an el_group under an HBM budget.
+
+    Admission is first come, first served, as in run_batched; an admitted request's plan
+    and buffers are built by a worker thread while the device steps the running members.
+    Each round of the loop enqueues about `run_ms` of steps (estimated from the running
+    members' cells at `rate_guess` cell-updates/s) and keeps at most one such run queued
+    behind the one the device is executing, so that joins and completions are seen within
+    a few milliseconds.  Withdrawal (cancel_at) works as in run_batched.  `pool`: where
+    plans are built (default: one worker thread).
+    """
+    pending = collections.deque(sorted(reqs, key=lambda q: q.arrival))
+    building = {}      # future -> request
+    members = {}       # slot -> (request, plan)
+    in_use = 0
+    own_pool = pool is None
+    if own_pool:
+        pool = concurrent.futures.ThreadPoolExecutor(max_workers=1)
+
+    def build(r):
+        plan = wl.plan(r)
+        inp, out = wl.io(r)
+        wl.settle()
+        return plan, inp, out
+
+    t0 = clock()
+    try:
+        while pending or building or members:
+            now = clock() - t0
+            changed = False
+            if any(r.cancel_at is not None and r.cancel_at <= now for r in pending):
+                keep = collections.deque()
+                for r in pending:
+                    if r.cancel_at is not None and r.cancel_at <= now:
+                        r.cancelled = True
+                        changed = True
+                    else:
+                        keep.append(r)
+                pending = keep
+            for slot in list(members):
+                r, plan = members[slot]
+                if not r.cancelled and r.cancel_at is not None and r.cancel_at <= now:
+                    r.cancelled = True
+                    r.output = None
+                    group.remove(slot)
+                    changed = True
+                _, done = group.poll(slot)
+                if done:
+                    members.pop(slot)
+                    if not r.cancelled:
+                        r.done = clock() - t0
+                    in_use -= r.bytes
+                    plan.close()
+                    changed = True
+            while (pending and pending[0].arrival <= now
+                   and len(members) + len(building) < group.max_members):
+                r = pending[0]
+                if r.bytes == 0:
+                    r.bytes = wl.footprint(r)
+                if r.bytes > budget_bytes:
+                    pending.popleft()
+                    r.rejected = True
+                    changed = True
+                    continue
+                if in_use + r.bytes > budget_bytes:
+                    break
+                pending.popleft()
+                in_use += r.bytes
+                building[pool.submit(build, r)] = r
+                changed = True
+            # in submission order (first come, first served), up to the first plan not built yet
+            while building and next(iter(building)).done():
+                fut = next(iter(building))
+                r = building.pop(fut)
+                plan, inp, out = fut.result()
+                if r.cancel_at is not None and r.cancel_at <= clock() - t0:
+                    r.cancelled = True
+                    in_use -= r.bytes
+                    plan.close()
+                else:
+                    slot = group.add(plan, r.op, inp, out)
+                    r.admitted = clock() - t0
+                    if wl.keep_outputs:
+                        r.output = out
+                    members[slot] = (r, plan)
+                changed = True
+            if trace is not None and changed:
+                trace.append((clock() - t0, in_use, len(members)))
+            running = [r for r, _ in members.values() if not r.cancelled]
+            if group.members()[2] > 0:
+                per_tick = sum(_cells(r) for r in running) / rate_guess
+                ticks = max(1, min(512, int(run_ms * 1e-3 / max(per_tick, 1e-7))))
+                group.run(ticks)
+                group.sync(1)
+            elif not changed:
+                if building:
+                    sleep(2e-4)
+                else:
+                    nxt = pending[0].arrival - (clock() - t0) if pending and not members else 0.0
+                    sleep(max(2e-4, min(nxt, 0.01)))
+        group.sync(0)
+    finally:
+        if own_pool:
+            pool.shutdown(wait=True)
+    return reqs
+
+
 def summarize(reqs) -> dict:
     done = [r for r in reqs if r.done is not None]
     if not done:
@@ -243,31 +384,41 @@ def summarize(reqs) -> dict:
                 mean_s=float(lat.mean()))
 
 
-def serve_benchmark(rates=(2, 5, 10, 20), count=200, sizes=SIZES, max_slots=4, chunk=64, budget=200e9, seed=0,
+def serve_benchmark(rates=(2, 5, 10, 20), count=200, sizes=SIZES, max_slots=8, chunk=64, budget=200e9, seed=0,
+                    modes=("plain", "grouped"), per_request_media=True,
                     log=lambda *a: print(*a, file=sys.stderr, flush=True)):
-    """Plain versus batched serving of the same request streams; one entry per rate."""
+    """Plain versus batched serving of the same request streams; one entry per rate, with a
+    summary per mode ("plain", "grouped": el_group, "executor": per-slot graph streams)."""
     import torch
     from . import el
-    wl = Workloads(sizes)
-    ex = el.Executor(max_slots=max_slots, chunk=chunk)
-    # warm both paths on one request per size (kernel loading, allocator growth)
+    wl = Workloads(sizes, per_request_media=per_request_media)
+    group = el.Group(max_members=max_slots) if "grouped" in modes else None
+    ex = el.Executor(max_slots=min(max_slots, 4), chunk=chunk) if "executor" in modes else None
+    runners = {"plain": lambda q: run_plain(q, wl),
+               "grouped": lambda q: run_grouped(q, wl, group, budget),
+               "executor": lambda q: run_batched(q, wl, ex, budget)}
+    # warm every path on one request per size (kernel loading, allocator growth)
     warm = [Request(rid=-1 - k, op=k % 2, n=n, nsteps=S.serving_steps(n), nrec=256, seed=k, arrival=0.0)
             for k, n in enumerate(sizes)]
-    run_plain(clone_requests(warm), wl)
-    run_batched(clone_requests(warm), wl, ex, budget)
+    for m in modes:
+        runners[m](clone_requests(warm))
     torch.cuda.synchronize()
     out = []
     for k, rate in enumerate(rates):
         reqs = request_mix(count, rate, seed=seed + k, sizes=sizes)
-        a = run_plain(clone_requests(reqs), wl)
-        b = run_batched(clone_requests(reqs), wl, ex, budget)
-        sa, sb = summarize(a), summarize(b)
-        ent = dict(rate=rate, count=count, plain=sa, batched=sb,
-                   throughput_gain=sb["gcells"] / sa["gcells"] if sa.get("gcells") else None)
-        log(f"[serve] rate {rate}/s: plain {sa['gcells']:.2f} Gcell/s p50 {sa['p50_s']:.2f}s p99 {sa['p99_s']:.2f}s | "
-            f"batched {sb['gcells']:.2f} Gcell/s p50 {sb['p50_s']:.2f}s p99 {sb['p99_s']:.2f}s")
+        ent = dict(rate=rate, count=count)
+        for m in modes:
+            ent[m] = summarize(runners[m](clone_requests(reqs)))
+            e = ent[m]
+            log(f"[serve] rate {rate}/s {m}: {e['gcells']:.2f} Gcell/s, {e['throughput_rps']:.2f} req/s, "
+                f"p50 {e['p50_s']:.2f}s p99 {e['p99_s']:.2f}s")
+        base = ent.get("plain", {}).get("gcells")
+        ent["throughput_gain"] = {m: ent[m]["gcells"] / base for m in modes if m != "plain"} if base else None
         out.append(ent)
-    ex.close()
+    if group is not None:
+        group.close()
+    if ex is not None:
+        ex.close()
     return out
 
 
@@ -275,13 +426,16 @@ def main():
     ap = argparse.ArgumentParser(description="plain vs batched serving of H / H^T requests")
     ap.add_argument("--rates", type=float, nargs="+", default=[2, 5, 10, 20])
     ap.add_argument("--count", type=int, default=200)
-    ap.add_argument("--slots", type=int, default=4)
+    ap.add_argument("--slots", type=int, default=8)
     ap.add_argument("--chunk", type=int, default=64)
     ap.add_argument("--budget-gb", type=float, default=200.0)
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--modes", nargs="+", default=["plain", "grouped"], choices=["plain", "grouped", "executor"])
+    ap.add_argument("--shared-media", action="store_true", help="one medium per size instead of one per request")
     args = ap.parse_args()
     res = serve_benchmark(rates=args.rates, count=args.count, max_slots=args.slots, chunk=args.chunk,
-                          budget=args.budget_gb * 1e9, seed=args.seed)
+                          budget=args.budget_gb * 1e9, seed=args.seed, modes=tuple(args.modes),
+                          per_request_media=not args.shared_media)
     print(json.dumps(res))
 
 

@@ -1,6 +1,8 @@
 """Serving scheduler logic on the CPU: a simulated clock and a mock executor stand in
 for the GPU, so admission, the HBM budget, slot limits and completion bookkeeping
 are checked without a device."""
+import concurrent.futures
+
 import numpy as np
 import pytest
 
@@ -39,6 +41,9 @@ class MockWorkloads:
 
     def io(self, r):
         return object(), object()
+
+    def settle(self):
+        pass
 
 
 class MockExecutor:
@@ -172,3 +177,124 @@ def test_cancelled_running_request_frees_its_slot_when_the_device_finishes():
     assert out[0].cancelled and out[0].output is None and out[0].done is None
     assert out[1].admitted >= dur and out[1].done is not None
     assert trace[-1][1] == 0 and trace[-1][2] == 0     # nothing held at the end
+
+
+class MockGroup:
+    """A simulated el_group: every tick advances each running member one step and takes
+    (sum of the running members' cells) / rate seconds of device time; run() enqueues,
+    sync(k) lets the simulated clock catch up with all but the last k runs."""
+
+    def __init__(self, clock, max_members=4, rate=5e9):
+        self.clock, self.max_members, self.rate = clock, max_members, rate
+        self.m = {}          # slot -> dict(req, steps, end, done_at, withdrawn)
+        self.dev_t = 0.0
+        self.runs = []
+        self.added = []
+        self.max_running = 0
+
+    def add(self, plan, op, inp, out):
+        free = [s for s in range(self.max_members) if s not in self.m]
+        assert free, "scheduler added a member without a free slot"
+        s = free[0]
+        r = plan.req
+        self.m[s] = dict(req=r, steps=0, total=r.nsteps - 1, done_at=None)
+        self.added.append(r.rid)
+        return s
+
+    def members(self):
+        run = sum(1 for v in self.m.values() if v["done_at"] is None)
+        return self.max_members, len(self.m), run
+
+    def run(self, ticks):
+        t = max(self.dev_t, self.clock())
+        for _ in range(ticks):
+            live = [v for v in self.m.values() if v["done_at"] is None]
+            if not live:
+                break
+            self.max_running = max(self.max_running, len(live))
+            t += sum(v["req"].n ** 3 for v in live) / self.rate
+            for v in live:
+                v["steps"] += 1
+                if v["steps"] == v["total"]:
+                    v["done_at"] = t
+        self.dev_t = t
+        self.runs.append(t)
+
+    def sync(self, pending=0):
+        while len(self.runs) > pending:
+            self.clock.t = max(self.clock.t, self.runs.pop(0))
+
+    def remove(self, slot):
+        v = self.m[slot]
+        if v["done_at"] is None:
+            v["done_at"] = max(self.dev_t, self.clock())
+
+    def poll(self, slot):
+        v = self.m[slot]
+        if v["done_at"] is not None and self.clock() >= v["done_at"]:
+            del self.m[slot]
+            return v["steps"], True
+        return v["steps"], False
+
+
+class SyncPool:
+    """Builds a plan at submission (the simulated clock does not see a worker thread)."""
+
+    def submit(self, fn, *args):
+        f = concurrent.futures.Future()
+        f.set_result(fn(*args))
+        return f
+
+
+def _run_grouped(reqs, budget, members=3, bpc=50):
+    clk = Clock()
+    g = MockGroup(clk, max_members=members)
+    trace = []
+    SV.run_grouped(reqs, TaggedWorkloads(bpc), g, budget_bytes=budget, clock=clk, sleep=clk.sleep, trace=trace,
+                   rate_guess=5e9, pool=SyncPool())
+    return reqs, trace, g
+
+
+def test_grouped_all_requests_complete_within_slots_and_budget():
+    reqs = SV.request_mix(40, rate=10.0, seed=1, sizes=(32, 48, 64))
+    budget = 64 ** 3 * 50 * 2.5
+    out, trace, g = _run_grouped(reqs, budget=budget, members=3)
+    assert all(r.done is not None and not r.rejected for r in out)
+    for r in out:
+        assert r.arrival <= r.admitted <= r.done
+    assert all(used <= budget for _, used, _ in trace)
+    assert max(a for _, _, a in trace) <= 3 and g.max_running <= 3
+    assert g.added == sorted(g.added)        # first come, first served
+    assert trace[-1][1] == 0 and trace[-1][2] == 0
+    s = SV.summarize(out)
+    assert s["n"] == 40 and s["p99_s"] >= s["p50_s"] > 0
+
+
+def test_grouped_requests_share_ticks():
+    """Requests that overlap in time step together: three arrivals at once finish after
+    about max(M) ticks of the three, not after the sum of their step counts."""
+    reqs = [SV.Request(rid=k, op=k % 2, n=32, nsteps=100 + 50 * k, nrec=8, seed=k, arrival=0.0) for k in range(3)]
+    out, trace, g = _run_grouped(reqs, budget=1e12, members=3)
+    tick_all = 3 * 32 ** 3 / 5e9
+    assert max(r.done for r in out) < 1.5 * 199 * tick_all
+    assert g.max_running == 3
+
+
+def test_grouped_withdrawal_while_waiting_and_running():
+    reqs = [SV.Request(rid=k, op=0, n=32, nsteps=200, nrec=8, seed=k, arrival=0.001 * k) for k in range(3)]
+    dur = reqs[0].cell_updates / 5e9
+    reqs[0].cancel_at = 0.3 * dur          # while it runs
+    reqs[2].cancel_at = 0.0005             # before it arrives: never admitted
+    out, trace, g = _run_grouped(reqs, budget=1e12, members=1)
+    assert out[0].cancelled and out[0].output is None and out[0].done is None
+    assert out[2].cancelled and out[2].admitted is None
+    assert out[1].done is not None and g.added == [0, 1]
+    assert trace[-1][1] == 0 and trace[-1][2] == 0
+
+
+def test_grouped_oversized_request_is_rejected():
+    reqs = SV.request_mix(6, rate=5.0, seed=3, sizes=(32,))
+    reqs[2].n = 200
+    out, trace, g = _run_grouped(reqs, budget=1e8)
+    assert out[2].rejected and out[2].done is None
+    assert all(r.done is not None for k, r in enumerate(out) if k != 2)

@@ -264,13 +264,13 @@ def _cells(r: Request) -> int:
 
 
 def run_grouped(reqs, wl, group, budget_bytes: float = 200e9, clock=time.perf_counter, sleep=time.sleep,
-                trace=None, run_ms: float = 2.0, rate_guess: float = 40e9, pool=None):
+                trace=None, run_ms: float = 2.0, rate_guess: float = 40e9, pool=None, ahead: int = 1):
     """Continuous batching over an el_group under an HBM budget.
 
     Admission is first come, first served, as in run_batched; an admitted request's plan
     and buffers are built by a worker thread while the device steps the running members.
     Each round of the loop enqueues about `run_ms` of steps (estimated from the running
-    members' cells at `rate_guess` cell-updates/s) and keeps at most one such run queued
+    members' cells at `rate_guess` cell-updates/s) and keeps at most `ahead` such runs queued
     behind the one the device is executing, so that joins and completions are seen within
     a few milliseconds.  Withdrawal (cancel_at) works as in run_batched.  `pool`: where
     plans are built (default: one worker thread).
@@ -357,7 +357,7 @@ def run_grouped(reqs, wl, group, budget_bytes: float = 200e9, clock=time.perf_co
                 per_tick = sum(_cells(r) for r in running) / rate_guess
                 ticks = max(1, min(512, int(run_ms * 1e-3 / max(per_tick, 1e-7))))
                 group.run(ticks)
-                group.sync(1)
+                group.sync(ahead)
             elif not changed:
                 if building:
                     sleep(2e-4)

@@ -269,6 +269,12 @@ el_status el_group_run(el_group g, int32_t ticks) {
     el_status st = check_group(g);
     if (st != EL_OK) return st;
     if (ticks < 0) return el::set_error(EL_EINVAL, "ticks must be >= 0");
+    // release the events of runs that have completed (a caller need not sync to keep the
+    // list short)
+    while (!g->runs.empty() && hipEventQuery(g->runs.front()) == hipSuccess) {
+        (void)hipEventDestroy(g->runs.front());
+        g->runs.erase(g->runs.begin());
+    }
     for (int t = 0; t < ticks; ++t) {
         bool any = false;
         for (auto &mb : g->m) any = any || mb.running;

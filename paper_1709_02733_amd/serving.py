@@ -11,10 +11,16 @@ them:
   workspaces and buffers of the admitted requests) allows it.  A worker
   thread builds its plan while the device works; it then joins the group,
   which advances all running requests one time step per tick with one
-  launch per sub-update for up to four requests at a time.  Requests leave
-  the group after their last step.
+  launch per sub-update for up to four requests at a time.  At most one
+  large request runs at a time and
+  small ones may pass a large one that waits (serve_benchmark's setting), so
+  small requests do not queue behind large ones.  Requests leave the group
+  after their last step.
 * executor (run_batched): each admitted request runs on its own slot stream
   as replays of captured step graphs, concurrently with the others.
+* hybrid (run_grouped with an executor): small requests join the group, large
+  ones (which fill the device alone) run on executor slots, and the two
+  overlap on the device.
 
 All paths run the same per-cell arithmetic in the same order per request, so
 each result is bitwise the same alone and in the mix.  The report gives
@@ -264,7 +270,8 @@ def _cells(r: Request) -> int:
 
 
 def run_grouped(reqs, wl, group, budget_bytes: float = 200e9, clock=time.perf_counter, sleep=time.sleep,
-                trace=None, run_ms: float = 2.0, rate_guess: float = 40e9, pool=None, ahead: int = 1):
+                trace=None, run_ms: float = 2.0, rate_guess: float = 40e9, pool=None, ahead: int = 1,
+                max_large: int | None = None, large_cells: int = 4_000_000, executor=None):
     """Continuous batching over an el_group under an HBM budget.
 
     Admission is first come, first served, as in run_batched; an admitted request's plan
@@ -274,10 +281,21 @@ def run_grouped(reqs, wl, group, budget_bytes: float = 200e9, clock=time.perf_co
     behind the one the device is executing, so that joins and completions are seen within
     a few milliseconds.  Withdrawal (cancel_at) works as in run_batched.  `pool`: where
     plans are built (default: one worker thread).
+
+    max_large: at most this many requests of >= large_cells cells run (or are being built)
+    at once; an arrived large request that waits for this cap lets later small requests
+    pass it, so small grids fill the launches of the large ones instead of several large
+    requests sharing the device step by step.  None: no cap (strict arrival order).
+
+    executor: large requests run on the executor's slots (a stream and captured step graphs
+    each, at most max_large of them if set) instead of in the group, so that the group's
+    small requests overlap with them on the device (hybrid mode).
     """
     pending = collections.deque(sorted(reqs, key=lambda q: q.arrival))
     building = {}      # future -> request
+    ready = []         # (request, plan, input, output) built, waiting to join
     members = {}       # slot -> (request, plan)
+    ex_active = {}     # executor slot -> (request, plan), hybrid mode
     in_use = 0
     own_pool = pool is None
     if own_pool:
@@ -291,7 +309,7 @@ def run_grouped(reqs, wl, group, budget_bytes: float = 200e9, clock=time.perf_co
 
     t0 = clock()
     try:
-        while pending or building or members:
+        while pending or building or ready or members or ex_active:
             now = clock() - t0
             changed = False
             if any(r.cancel_at is not None and r.cancel_at <= now for r in pending):
@@ -318,40 +336,88 @@ def run_grouped(reqs, wl, group, budget_bytes: float = 200e9, clock=time.perf_co
                     in_use -= r.bytes
                     plan.close()
                     changed = True
-            while (pending and pending[0].arrival <= now
-                   and len(members) + len(building) < group.max_members):
-                r = pending[0]
+            for slot in list(ex_active):
+                r, plan = ex_active[slot]
+                if not r.cancelled and r.cancel_at is not None and r.cancel_at <= now:
+                    r.cancelled = True
+                    r.output = None
+                    changed = True
+                if executor.poll(slot):
+                    ex_active.pop(slot)
+                    if not r.cancelled:
+                        r.done = clock() - t0
+                    in_use -= r.bytes
+                    plan.close()
+                    changed = True
+            is_large = lambda q: _cells(q) >= large_cells
+            # a request is built ahead of its turn (one beyond the free slots, and one large
+            # request beyond the cap), so that its plan is ready when the device can take it
+            ex_slots = executor.max_slots if executor is not None else 0
+            large_cap = max_large if max_large is not None else (ex_slots if executor is not None else None)
+            queued = len(members) + len(ex_active) + len(building) + len(ready)
+            n_large = (sum(1 for q, _ in members.values() if is_large(q)) + len(ex_active)
+                       + sum(1 for q in building.values() if is_large(q)) + sum(1 for q, *_ in ready if is_large(q)))
+            idx = 0
+            while idx < len(pending) and pending[idx].arrival <= now and queued < group.max_members + ex_slots + 1:
+                r = pending[idx]
                 if r.bytes == 0:
                     r.bytes = wl.footprint(r)
                 if r.bytes > budget_bytes:
-                    pending.popleft()
+                    del pending[idx]
                     r.rejected = True
                     changed = True
                     continue
                 if in_use + r.bytes > budget_bytes:
                     break
-                pending.popleft()
+                if is_large(r) and large_cap is not None and n_large >= large_cap + 1:
+                    idx += 1          # waits for the cap; later small requests may pass it
+                    continue
+                del pending[idx]
                 in_use += r.bytes
+                queued += 1
+                n_large += 1 if is_large(r) else 0
                 building[pool.submit(build, r)] = r
                 changed = True
-            # in submission order (first come, first served), up to the first plan not built yet
+            # built plans in submission order, up to the first plan not built yet
             while building and next(iter(building)).done():
                 fut = next(iter(building))
                 r = building.pop(fut)
-                plan, inp, out = fut.result()
+                ready.append((r,) + tuple(fut.result()))
+                changed = True
+            # join the group in admission order; a large request that waits for the cap lets
+            # later small ones pass it
+            large_running = sum(1 for q, _ in members.values() if is_large(q)) + len(ex_active)
+            k = 0
+            while k < len(ready):
+                r, plan, inp, out = ready[k]
                 if r.cancel_at is not None and r.cancel_at <= clock() - t0:
+                    del ready[k]
                     r.cancelled = True
                     in_use -= r.bytes
                     plan.close()
+                    changed = True
+                    continue
+                large = is_large(r)
+                to_executor = large and executor is not None
+                if ((large and large_cap is not None and large_running >= large_cap)
+                        or (to_executor and len(ex_active) >= ex_slots)
+                        or (not to_executor and len(members) >= group.max_members)):
+                    k += 1
+                    continue
+                del ready[k]
+                if to_executor:
+                    slot = executor.start(plan, r.op, inp, out)
+                    ex_active[slot] = (r, plan)
                 else:
                     slot = group.add(plan, r.op, inp, out)
-                    r.admitted = clock() - t0
-                    if wl.keep_outputs:
-                        r.output = out
                     members[slot] = (r, plan)
+                r.admitted = clock() - t0
+                if wl.keep_outputs:
+                    r.output = out
+                large_running += 1 if large else 0
                 changed = True
             if trace is not None and changed:
-                trace.append((clock() - t0, in_use, len(members)))
+                trace.append((clock() - t0, in_use, len(members) + len(ex_active)))
             running = [r for r, _ in members.values() if not r.cancelled]
             if group.members()[2] > 0:
                 per_tick = sum(_cells(r) for r in running) / rate_guess
@@ -359,7 +425,7 @@ def run_grouped(reqs, wl, group, budget_bytes: float = 200e9, clock=time.perf_co
                 group.run(ticks)
                 group.sync(ahead)
             elif not changed:
-                if building:
+                if building or ready or ex_active:
                     sleep(2e-4)
                 else:
                     nxt = pending[0].arrival - (clock() - t0) if pending and not members else 0.0
@@ -392,11 +458,12 @@ def serve_benchmark(rates=(2, 5, 10, 20), count=200, sizes=SIZES, max_slots=8, c
     import torch
     from . import el
     wl = Workloads(sizes, per_request_media=per_request_media)
-    group = el.Group(max_members=max_slots) if "grouped" in modes else None
-    ex = el.Executor(max_slots=min(max_slots, 4), chunk=chunk) if "executor" in modes else None
+    group = el.Group(max_members=max_slots) if ("grouped" in modes or "hybrid" in modes) else None
+    ex = el.Executor(max_slots=min(max_slots, 4), chunk=chunk) if ("executor" in modes or "hybrid" in modes) else None
     runners = {"plain": lambda q: run_plain(q, wl),
-               "grouped": lambda q: run_grouped(q, wl, group, budget),
-               "executor": lambda q: run_batched(q, wl, ex, budget)}
+               "grouped": lambda q: run_grouped(q, wl, group, budget, max_large=1),
+               "executor": lambda q: run_batched(q, wl, ex, budget),
+               "hybrid": lambda q: run_grouped(q, wl, group, budget, executor=ex)}
     # warm every path on one request per size (kernel loading, allocator growth)
     warm = [Request(rid=-1 - k, op=k % 2, n=n, nsteps=S.serving_steps(n), nrec=256, seed=k, arrival=0.0)
             for k, n in enumerate(sizes)]
@@ -430,7 +497,7 @@ def main():
     ap.add_argument("--chunk", type=int, default=64)
     ap.add_argument("--budget-gb", type=float, default=200.0)
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--modes", nargs="+", default=["plain", "grouped"], choices=["plain", "grouped", "executor"])
+    ap.add_argument("--modes", nargs="+", default=["plain", "grouped"], choices=["plain", "grouped", "executor", "hybrid"])
     ap.add_argument("--shared-media", action="store_true", help="one medium per size instead of one per request")
     args = ap.parse_args()
     res = serve_benchmark(rates=args.rates, count=args.count, max_slots=args.slots, chunk=args.chunk,

@@ -103,6 +103,36 @@ def test_members_equal_direct_calls(precision):
     grp.close()
 
 
+def test_large_and_small_members_share_launches():
+    """A 160^3 forward and a 162 x 160 x 158 adjoint (several thousand tiles each) in the
+    same grouped launches as two small members: all bitwise equal to direct calls."""
+    shapes = [((160, 160, 160), el.OP_FORWARD), ((162, 160, 158), el.OP_ADJOINT),
+              ((40, 33, 29), el.OP_FORWARD), ((29, 41, 19), el.OP_ADJOINT)]
+    ms = []
+    for k, (shape, op) in enumerate(shapes):
+        sc = S.random_scenario(shape, seed=20 + k, nsteps=17 + 3 * k, npml=4, nrec=25, fluid_fraction=0.7)
+        plan = el.Plan.from_scenario(sc)
+        if op == el.OP_FORWARD:
+            inp = torch.from_numpy(sc.p0).to(plan.device)
+            ref = plan.forward(inp).clone()
+        else:
+            inp = torch.randn((sc.nsteps, sc.nrec), dtype=torch.float64, generator=torch.Generator().manual_seed(k)).cuda()
+            ref = plan.adjoint(inp).clone()
+        ms.append((plan, op, inp, ref))
+    assert ms[0][0].grid.nx * ms[0][0].grid.ny * ms[0][0].grid.nz >= 4000000
+    grp = el.Group(max_members=4)
+    outs = [torch.full_like(ref, float("nan")) for *_, ref in ms]
+    slots = [grp.add(plan, op, inp, outs[k]) for k, (plan, op, inp, _) in enumerate(ms)]
+    while grp.members()[2]:
+        grp.run(5)
+        grp.sync(1)
+    grp.sync(0)
+    for k, s in enumerate(slots):
+        assert grp.poll(s)[1]
+        assert torch.equal(outs[k], ms[k][3]), k
+    grp.close()
+
+
 def test_withdrawn_member_leaves_the_others_unchanged():
     ms = [_member(k, "f32") for k in (0, 1, 3)]
     grp = el.Group(max_members=3)
@@ -178,6 +208,22 @@ def test_grouped_serving_equals_plain_at_96_and_128(serving_96_128):
         assert rb.done is not None
         assert torch.equal(ra.output, rb.output), (ra.rid, ra.n, ra.op)
     grp.close()
+
+
+def test_hybrid_serving_equals_plain(serving_96_128):
+    """Hybrid mode (128^3 requests on executor slots, 96^3 ones in the group, overlapping on
+    the device): bitwise the plain path's results."""
+    wl, reqs = serving_96_128
+    grp = el.Group(max_members=4)
+    ex = el.Executor(max_slots=2, chunk=16)
+    a = SV.run_plain(SV.clone_requests(reqs), wl)
+    b = SV.run_grouped(SV.clone_requests(reqs), wl, grp, budget_bytes=1e12, executor=ex, large_cells=128 ** 3)
+    for ra, rb in zip(a, b):
+        assert rb.done is not None
+        assert torch.equal(ra.output, rb.output), (ra.rid, ra.n, ra.op)
+    assert grp.members()[1] == 0 and ex.slots()[1] == 0
+    grp.close()
+    ex.close()
 
 
 def test_grouped_serving_matches_the_oracle_at_96(serving_96_128):

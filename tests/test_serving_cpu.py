@@ -298,3 +298,57 @@ def test_grouped_oversized_request_is_rejected():
     out, trace, g = _run_grouped(reqs, budget=1e8)
     assert out[2].rejected and out[2].done is None
     assert all(r.done is not None for k, r in enumerate(out) if k != 2)
+
+
+def test_grouped_cap_on_large_requests_lets_small_ones_pass():
+    """max_large = 1: never two large requests in the group at once; a small request that
+    arrives behind a waiting large one joins before it."""
+    reqs = [SV.Request(rid=0, op=0, n=64, nsteps=200, nrec=8, seed=0, arrival=0.0),
+            SV.Request(rid=1, op=1, n=64, nsteps=200, nrec=8, seed=1, arrival=0.001),
+            SV.Request(rid=2, op=0, n=24, nsteps=100, nrec=8, seed=2, arrival=0.002)]
+    clk = Clock()
+    g = MockGroup(clk, max_members=4)
+    large = []
+    orig_run = g.run
+
+    def run(ticks):
+        live = [v["req"].rid for v in g.m.values() if v["done_at"] is None and v["req"].n == 64]
+        large.append(len(live))
+        orig_run(ticks)
+
+    g.run = run
+    SV.run_grouped(reqs, TaggedWorkloads(), g, budget_bytes=1e12, clock=clk, sleep=clk.sleep, rate_guess=5e9,
+                   pool=SyncPool(), max_large=1, large_cells=48 ** 3)
+    assert max(large) == 1
+    assert g.added == [0, 2, 1]
+    assert all(r.done is not None for r in reqs)
+    assert reqs[2].admitted < reqs[1].admitted
+
+
+def test_hybrid_sends_large_requests_to_the_executor():
+    """Hybrid mode: requests of >= large_cells cells start on executor slots (at most its
+    slot count at once), the others join the group; all complete within the budget."""
+    reqs = SV.request_mix(30, rate=20.0, seed=9, sizes=(24, 32, 64))
+    clk = Clock()
+    g = MockGroup(clk, max_members=4)
+    ex = MockExecutor(clk, max_slots=2)
+    started = []
+    orig_start = ex.start
+
+    def start(plan, op, inp, out):
+        ex._dur = plan.req.cell_updates / ex.rate
+        started.append(plan.req.rid)
+        assert len(ex.busy) < ex.max_slots
+        return orig_start(plan, op, inp, out)
+
+    ex.start = start
+    budget = 64 ** 3 * 50 * 3.5
+    trace = []
+    SV.run_grouped(reqs, TaggedWorkloads(), g, budget_bytes=budget, clock=clk, sleep=clk.sleep, trace=trace,
+                   rate_guess=5e9, pool=SyncPool(), executor=ex, large_cells=48 ** 3)
+    large = {r.rid for r in reqs if r.n == 64}
+    assert set(started) == large and len(started) == len(large)
+    assert set(g.added) == {r.rid for r in reqs} - large
+    assert all(r.done is not None for r in reqs)
+    assert all(used <= budget for _, used, _ in trace)
+    assert trace[-1][1] == 0 and trace[-1][2] == 0

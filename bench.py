@@ -380,7 +380,7 @@ def main():
                           "request at a time through el_forward/el_adjoint; grouped = el_group with 8 slots "
                           "(up to 4 requests per launch, at most one request of >= 4M cells, plans built on a "
                           "worker thread); executor = el_exec with 4 slots (a stream each, captured 64-step "
-                          "graphs); hybrid = requests of >= 4M cells on the executor, the others in the group",
+                          "graphs); hybrid = requests of >= 4M cells on 2 executor slots, the others in the group",
                    "rates": [dict({m: {k: e[m][k] for k in keys} for m in modes}, rate=e["rate"],
                                   throughput_gain=e["throughput_gain"]) for e in res]}
 

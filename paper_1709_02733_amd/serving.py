@@ -461,10 +461,8 @@ def serve_benchmark(rates=(2, 5, 10, 20), count=200, sizes=SIZES, max_slots=8, c
     wl = Workloads(sizes, per_request_media=per_request_media)
     group = el.Group(max_members=max_slots) if ("grouped" in modes or "hybrid" in modes) else None
     ex = el.Executor(max_slots=min(max_slots, 4), chunk=chunk) if "executor" in modes else None
-    # hybrid: two executor slots for the large requests (measured at 10 and 20 req/s: as much
-    # throughput as four, with a lower median and p99, since fewer large requests share the
-    # device at a time)
-    ex_h = el.Executor(max_slots=2, chunk=chunk) if "hybrid" in modes else None
+    # hybrid: its own executor (four slots) for the large requests
+    ex_h = el.Executor(max_slots=min(max_slots, 4), chunk=chunk) if "hybrid" in modes else None
     runners = {"plain": lambda q: run_plain(q, wl),
                "grouped": lambda q: run_grouped(q, wl, group, budget, max_large=1),
                "executor": lambda q: run_batched(q, wl, ex, budget),

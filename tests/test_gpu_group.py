@@ -184,6 +184,40 @@ def test_group_rejects_bad_members():
     grp.close()
 
 
+def test_group_call_edges():
+    """run / sync / poll / remove on an empty group, a free slot, a member that has taken
+    some steps, and out-of-range arguments."""
+    plan, op, inp, ref = _member(0, "f32")
+    grp = el.Group(max_members=2)
+    grp.run(0)
+    grp.run(5)                                   # nothing to step
+    grp.sync(0)
+    assert grp.poll(1) == (0, True)              # a free slot is done
+    grp.remove(1)                                # withdrawing a free slot does nothing
+    out = torch.empty_like(ref)
+    s = grp.add(plan, op, inp, out)
+    assert grp.poll(s) == (0, False)
+    grp.run(3)
+    grp.sync(0)
+    assert grp.poll(s) == (3, False)
+    assert grp.members() == (2, 1, 1)
+    for bad in (lambda: grp.run(-1), lambda: grp.sync(-1), lambda: grp.poll(2), lambda: grp.remove(-1)):
+        with pytest.raises(el.ElError) as ei:
+            bad()
+        assert ei.value.status == el.EL_EINVAL
+    grp.remove(s)
+    grp.sync(0)
+    assert grp.poll(s) == (3, True)
+    assert grp.members() == (2, 0, 0)
+    # the plan runs again, in the group, to the direct call's result
+    s = grp.add(plan, op, inp, out)
+    while grp.members()[2]:
+        grp.run(16)
+    grp.sync(0)
+    assert grp.poll(s)[1] and torch.equal(out, ref)
+    grp.close()
+
+
 @pytest.fixture(scope="module")
 def serving_96_128():
     wl = SV.Workloads(sizes=(96, 128), keep_outputs=True, per_request_media=True)

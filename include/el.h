@@ -466,8 +466,9 @@ el_status el_group_add(el_group g, el_plan plan, int32_t op, const void *in, voi
 el_status el_group_run(el_group g, int32_t ticks);
 
 /* Block until at most `pending` of the el_group_run calls so far are still
- * running on the device (pending = 0: all done).  Bounds how far the host
- * runs ahead of the device, and releases the calls' events. */
+ * running on the device; pending = 0: until everything enqueued on the group
+ * (runs, joins, withdrawals) has completed.  Bounds how far the host runs
+ * ahead of the device, and releases the calls' events. */
 el_status el_group_sync(el_group g, int32_t pending);
 
 /* Non-blocking: *steps_done = steps enqueued for the slot's member so far;

@@ -293,6 +293,13 @@ el_status el_group_sync(el_group g, int32_t pending) {
     el_status st = check_group(g);
     if (st != EL_OK) return st;
     if (pending < 0) return el::set_error(EL_EINVAL, "pending must be >= 0");
+    if (pending == 0) {
+        // everything enqueued so far (runs, joins, withdrawals) has completed
+        GR_TRY(hipStreamSynchronize(g->stream), "wait for the group");
+        for (auto &e : g->runs) (void)hipEventDestroy(e);
+        g->runs.clear();
+        return EL_OK;
+    }
     while ((int)g->runs.size() > pending) {
         GR_TRY(hipEventSynchronize(g->runs.front()), "wait for a run");
         (void)hipEventDestroy(g->runs.front());

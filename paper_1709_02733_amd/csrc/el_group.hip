@@ -242,6 +242,10 @@ el_status el_group_add(el_group g, el_plan plan, int32_t op, const void *in, voi
         if (k < 0 && !g->m[q].used) k = q;
     }
     if (k < 0) return el::set_error(EL_EBUSY, "all %d group slots are in use", (int)g->m.size());
+    // the caller's stream may still be writing the input; the plan's previous operation may run
+    GR_TRY(hipEventRecord(g->ready, reinterpret_cast<hipStream_t>(stream)), "record the caller's stream");
+    GR_TRY(hipStreamWaitEvent(g->stream, g->ready, 0), "order after the caller's stream");
+    GR_TRY(hipStreamWaitEvent(g->stream, plan->done, 0), "order after the plan's previous operation");
     Member &mb = g->m[k];
     mb.used = true;
     mb.withdrawn = false;
@@ -251,10 +255,6 @@ el_status el_group_add(el_group g, el_plan plan, int32_t op, const void *in, voi
     mb.out = out;
     mb.steps = 0;
     mb.total = plan->g.nsteps - 1;
-    // the caller's stream may still be writing the input; the plan's previous operation may run
-    GR_TRY(hipEventRecord(g->ready, reinterpret_cast<hipStream_t>(stream)), "record the caller's stream");
-    GR_TRY(hipStreamWaitEvent(g->stream, g->ready, 0), "order after the caller's stream");
-    GR_TRY(hipStreamWaitEvent(g->stream, plan->done, 0), "order after the plan's previous operation");
     st = g->precision == EL_F64 ? start<double>(g, mb) : start<float>(g, mb);
     if (st != EL_OK) {
         (void)hipStreamSynchronize(g->stream);

@@ -734,11 +734,12 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
     }
     bool fl, ul, rowuni;
     const bool row = fluid_row(tl, t, x0, y0, d.nx, d.ny, cols, fl, ul, rowuni);
-    if (row || (ADJ && fl)) {
-        // fluid wavefront of a general tile (or, in the adjoint, whose general loop has no
-        // registers to spare for the masked loads, a fluid lane of a mixed wavefront, which
-        // then executes both loops): its neighbours read s22 and s33, so all are stored
-        if (row && rowuni) fluid_str<T, ADJ, true>(d, i, j, y0, z0, z1, o, t, 0, true, true, snx, sny, sox, soy);
+    if (row) {
+        // fluid wavefront of a general tile: its neighbours read s22 and s33, so all are stored
+        // (the fluid lanes of a mixed wavefront run the general loop below with masked loads,
+        // in the adjoint too: with its arguments addressed by member, the grouped build the
+        // adjoint takes has the registers for it, and the wavefront runs one loop, not both)
+        if (rowuni) fluid_str<T, ADJ, true>(d, i, j, y0, z0, z1, o, t, 0, true, true, snx, sny, sox, soy);
         else fluid_str<T, ADJ, false>(d, i, j, y0, z0, z1, o, t, 0, true, ul, snx, sny, sox, soy);
         if (ADJ && yrow) scatter_col(d, r, yrow, t);
         return;

@@ -423,8 +423,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
         return;
     }
     const bool sh = !fl;                     // this lane reads the shear stresses
-    const bool mp = ADJ || !ul;              // this lane reads rho and alpha from the maps (the
-                                             // adjoint has no registers to spare for the choice)
+    const bool mp = !ul;                     // this lane reads rho and alpha from the maps
     const T rho_t = d.med[4 * t + 1], alp_t = d.med[4 * t + 2];
     // s22 and s33 hold s11's value on a fluid lane's taps (fluid columns store all three,
     // fluid tiles the bands next to general tiles), so every lane reads them from their own
@@ -896,10 +895,12 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
     if (ADJ && yrow) scatter_col(d, r, yrow, t);
 }
 
-// A plan's own pass as a launch of one member.  The adjoint stress pass takes the grouped
-// kernel (G = kGroupMax) with one member: with its kernel arguments addressed by member the
-// compiler keeps fewer of them in registers, and the pass runs in 419 instead of 443 us at
-// 384^3 (the other passes are as fast or faster with G = 1).
+// A plan's own pass as a launch of one member.  The adjoint passes take the grouped kernels
+// (G = kGroupMax) with one member: with their kernel arguments addressed by member the
+// compiler keeps fewer of them in registers, which leaves room for the masked loads of their
+// mixed rows (at 384^3 the adjoint stress pass runs in 398 instead of 443 us, the adjoint
+// velocity pass reads the maps only off uniform lanes); the forward passes are as fast with
+// G = 1.
 template <int G, typename T>
 Grp<T, G> one(const Dev<T> &d, const Tiles &tl, const Rec *r = nullptr, double *row = nullptr) {
     Grp<T, G> g{};
@@ -932,7 +933,8 @@ hipError_t launch_stress(const Dev<T> &d, const Tiles &tl, hipStream_t s, int *c
 }
 template <typename T>
 hipError_t launch_adj_velocity(const Dev<T> &d, const Tiles &tl, hipStream_t s, int *ctr) {
-    hipLaunchKernelGGL((k_vel<T, true, false, 1>), dim3(8 * tl.per), dim3(NT), 0, s, one<1>(d, tl), (double *)nullptr,
+    hipLaunchKernelGGL((k_vel<T, true, false, kGroupMax>), dim3(8 * tl.per), dim3(NT), 0, s, one<kGroupMax>(d, tl),
+                       (double *)nullptr,
                        ctr);
     return hipGetLastError();
 }

@@ -379,7 +379,7 @@ def main():
                           "60% forward / 40% adjoint, Poisson arrivals, 200 GB HBM budget; plain = one "
                           "request at a time through el_forward/el_adjoint; executor = el_exec with 4 slots "
                           "(a stream each, captured 64-step "
-                          "graphs); hybrid = requests of >= 4M cells on 4 executor slots, the others in an el_group "
+                          "graphs); hybrid = requests of >= 4M cells on 2 executor slots, the others in an el_group "
                           "(8 slots, up to 4 requests per launch, plans built on a worker thread)",
                    "rates": [dict({m: {k: e[m][k] for k in keys} for m in modes}, rate=e["rate"],
                                   throughput_gain=e["throughput_gain"]) for e in res]}

@@ -451,7 +451,7 @@ def summarize(reqs) -> dict:
 
 
 def serve_benchmark(rates=(2, 5, 10, 20), count=200, sizes=SIZES, max_slots=8, chunk=64, budget=200e9, seed=0,
-                    modes=("plain", "hybrid"), per_request_media=True,
+                    modes=("plain", "executor"), per_request_media=True,
                     log=lambda *a: print(*a, file=sys.stderr, flush=True)):
     """Plain versus batched serving of the same request streams; one entry per rate, with a
     summary per mode ("plain"; "grouped": el_group; "executor": per-slot graph streams;
@@ -503,7 +503,7 @@ def main():
     ap.add_argument("--chunk", type=int, default=64)
     ap.add_argument("--budget-gb", type=float, default=200.0)
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--modes", nargs="+", default=["plain", "hybrid"], choices=["plain", "grouped", "executor", "hybrid"])
+    ap.add_argument("--modes", nargs="+", default=["plain", "executor"], choices=["plain", "grouped", "executor", "hybrid"])
     ap.add_argument("--shared-media", action="store_true", help="one medium per size instead of one per request")
     args = ap.parse_args()
     res = serve_benchmark(rates=args.rates, count=args.count, max_slots=args.slots, chunk=args.chunk,

@@ -1,8 +1,7 @@
 """Serving forward and adjoint applications of many reconstructions at once.
 
 Requests (a forward H p0 or an adjoint H^T y, each on its own grid, medium,
-step count and receiver set) arrive as a Poisson stream.  Two ways to serve
-them:
+step count and receiver set) arrive as a Poisson stream.  Ways to serve them:
 
 * plain: first come, first served, one request at a time, each through
   el_forward / el_adjoint with per-step kernel launches.
@@ -12,22 +11,23 @@ them:
   thread builds its plan while the device works; it then joins the group,
   which advances all running requests one time step per tick with one
   launch per sub-update for up to four requests at a time.  At most one
-  large request runs at a time and
-  small ones may pass a large one that waits (serve_benchmark's setting), so
-  small requests do not queue behind large ones.  Requests leave the group
-  after their last step.
+  large request runs at a time and small ones may pass a large one that
+  waits (serve_benchmark's setting), so small requests do not queue behind
+  large ones.  Requests leave the group after their last step.
 * executor (run_batched): each admitted request runs on its own slot stream
-  as replays of captured step graphs, concurrently with the others.
+  as replays of captured step graphs, concurrently with the others (the
+  steadiest throughput gain over plain).
 * hybrid (run_grouped with an executor): small requests join the group, large
   ones (which fill the device alone) run on executor slots, and the two
-  overlap on the device.
+  overlap on the device; its gain depends on how the process's streams share
+  the hardware queues.
 
 All paths run the same per-cell arithmetic in the same order per request, so
 each result is bitwise the same alone and in the mix.  The report gives
 throughput (requests/s and Gcell-updates/s) and p50/p99 latency (arrival to
 result) per arrival rate.
 
-    python -m paper_1709_02733_amd.serving --rates 2 5 10 20 --count 200
+    python -m paper_1709_02733_amd.serving --rates 2 5 10 20 --count 100 --modes plain executor grouped hybrid
 """
 from __future__ import annotations
 

@@ -370,7 +370,7 @@ def main():
         from paper_1709_02733_amd import serving as SV
         del plan, p0, traces, padj
         torch.cuda.empty_cache()
-        modes = ("plain", "hybrid", "executor")
+        modes = ("plain", "executor", "grouped")
         res = SV.serve_benchmark(rates=args.serving_rates, count=args.serving_count, modes=modes, log=log)
         keys = ("gcells", "throughput_rps", "p50_s", "p99_s")
         serving = {"requests_per_rate": args.serving_count,
@@ -378,9 +378,8 @@ def main():
                           "speeds and density scaled up to 3%), 800-1800 samples, 256-1024 receivers, "
                           "60% forward / 40% adjoint, Poisson arrivals, 200 GB HBM budget; plain = one "
                           "request at a time through el_forward/el_adjoint; executor = el_exec with 4 slots "
-                          "(a stream each, captured 64-step "
-                          "graphs); hybrid = requests of >= 4M cells on 2 executor slots, the others in an el_group "
-                          "(8 slots, up to 4 requests per launch, plans built on a worker thread)",
+                          "(a stream each, captured 64-step graphs); grouped = el_group with 8 slots (up to 4 "
+                          "requests per launch, at most one request of >= 4M cells, plans built on a worker thread)",
                    "rates": [dict({m: {k: e[m][k] for k in keys} for m in modes}, rate=e["rate"],
                                   throughput_gain=e["throughput_gain"]) for e in res]}
 

@@ -236,11 +236,12 @@ __device__ __forceinline__ void scatter_point(const Dev<T> &d, const Rec &r, con
 }
 
 // Arguments of a stencil launch over the tiles of G plans of one precision (G = 1: a plan's
-// own passes; G = kGroupMax: the grouped passes of el_group).  Member q owns blocks
-// first[q] .. first[q+1]-1; each first[q] is a multiple of 8, so that the member's block
-// b - first[q] runs on XCD (b - first[q]) % 8 as its tile order assumes.  Entries past the
-// last member repeat the total block count.  row[q]: the trace row that member's gather
-// blocks write (forward velocity launch) or its scatter reads (grouped scatter), or null.
+// own forward passes; G = kGroupMax: the grouped passes of el_group, and a plan's own
+// adjoint passes as one member).  Member q owns blocks first[q] .. first[q+1]-1; each
+// first[q] is a multiple of 8, so that the member's block b - first[q] runs on XCD
+// (b - first[q]) % 8 as its tile order assumes.  Entries past the last member repeat the
+// total block count (or lie beyond every block).  row[q]: the trace row that member's gather
+// blocks write (forward velocity launch) or its adjoint stress launch scatters, or null.
 constexpr int kGroupMax = 4;
 template <typename T, int G>
 struct Grp {

@@ -462,10 +462,10 @@ def serve_benchmark(rates=(2, 5, 10, 20), count=200, sizes=SIZES, max_slots=8, c
     group = el.Group(max_members=max_slots) if ("grouped" in modes or "hybrid" in modes) else None
     ex = el.Executor(max_slots=min(max_slots, 4), chunk=chunk) if "executor" in modes else None
     # hybrid: its own executor with two slots for the large requests.  With the group's stream
-    # and the caller's, two executor streams keep every stream on a hardware queue of its own
-    # (four per process); with more, the group's small launches can wait in a queue behind a
-    # large request's graph (measured on 40 requests at 10 req/s: median latency 1.3 s with
-    # two slots, 3.7 and 2.9 s with three and four)
+    # and the caller's, two executor streams can each have a hardware queue of their own (four
+    # per process); with more, the group's small launches may wait in a queue behind a large
+    # request's graph (measured on 40 requests at 10 req/s: median latency 1.3 s with two
+    # slots, 3.7 and 2.9 s with three and four)
     ex_h = el.Executor(max_slots=2, chunk=chunk) if "hybrid" in modes else None
     runners = {"plain": lambda q: run_plain(q, wl),
                "grouped": lambda q: run_grouped(q, wl, group, budget, max_large=1),

@@ -379,7 +379,10 @@ el_status el_plan_kernel_time(el_plan plan, int32_t kind, int64_t *launches, dou
  * slot and returns at once: the initial state, then the time loop as replays
  * of a captured graph of `chunk_steps` steps (a device step counter selects
  * the trace row, so one graph serves every chunk), then the extraction of the
- * adjoint.  Operations on different slots overlap on the device.  Results are
+ * adjoint.  Operations on different slots overlap on the device.  With a
+ * replay limit (el_exec_set_ahead) a slot holds at most that many replays in
+ * flight and el_exec_poll / el_exec_pump / el_exec_wait enqueue the rest as
+ * earlier ones complete, so the host must keep calling them.  Results are
  * identical to el_forward / el_adjoint on the same plan.  The operation is
  * ordered after the plan's previous operation; the plan must not be used
  * again, nor its buffers released, before el_exec_poll reports completion.
@@ -413,6 +416,18 @@ el_status el_exec_wait(el_exec ex, int32_t slot);
 
 /* Number of slots and how many are running an operation. */
 el_status el_exec_slots(el_exec ex, int32_t *total, int32_t *busy);
+
+/*
+ * Replays of the step graph each slot keeps in flight: 0 (the default) enqueues
+ * an operation whole at el_exec_start; r in 1..1024 enqueues r replays there and
+ * the rest from el_exec_poll / el_exec_pump / el_exec_wait as earlier replays
+ * complete, which bounds how much of one slot's work is queued ahead of other
+ * streams.  EL_EBUSY while a slot is running; EL_EINVAL for r outside 0..1024.
+ */
+el_status el_exec_set_ahead(el_exec ex, int32_t replays);
+
+/* Non-blocking: enqueue what the replay limit allows on every running slot. */
+el_status el_exec_pump(el_exec ex);
 
 /*
  * Group: grouped time stepping of many operations (serving).

@@ -3,7 +3,11 @@
 // An executor owns a few slots, each with its own HIP stream.  Starting an
 // operation on a slot enqueues all of it at once: the initial state (direct
 // launches), then the time loop as replays of a captured graph of K steps,
-// then the final extraction.  The trace row of each step comes from a device
+// then the final extraction.  With a replay limit (el_exec_set_ahead) only that
+// many replays are in flight per slot; el_exec_poll / el_exec_pump / el_exec_wait
+// enqueue the next ones as earlier ones complete, so a slot's stream never holds
+// more than that much queued work ahead of other streams sharing its hardware
+// queue.  The trace row of each step comes from a device
 // counter that the step's own kernels advance, so the same K-step graph is
 // valid for every chunk.  Operations on different slots run concurrently on the
 // device; the host only polls completion events, so it is free to build the
@@ -22,6 +26,15 @@ struct ExecSlot {
     hipEvent_t ready = nullptr;   // inputs written: recorded on the caller's stream
     el_plan plan = nullptr;
     hipGraphExec_t graph[2] = {nullptr, nullptr};
+    // what is left of the operation to enqueue (replay limit)
+    int op = EL_OP_FORWARD;
+    const void *in = nullptr;
+    void *out = nullptr;
+    int full_left = 0;            // K-step replays not yet enqueued
+    bool rem_left = false;        // the remainder replay not yet enqueued
+    bool tail_done = true;        // the final work and completion events are enqueued
+    std::vector<hipEvent_t> ring; // one event after each replay in flight (ahead > 0)
+    int head = 0, count = 0;
 };
 
 }  // namespace
@@ -29,6 +42,7 @@ struct ExecSlot {
 struct el_exec_ {
     int device = 0;
     int chunk = 64;
+    int ahead = 0;                // replays in flight per slot; 0 = all at once
     std::vector<ExecSlot> slots;
 };
 
@@ -84,6 +98,47 @@ el_status capture(el_plan p, const Dev<T> &d, int op, int steps, void *traces, i
     return EL_OK;
 }
 
+// Enqueue the slot's remaining replays, at most ex->ahead of them in flight (all when
+// ahead = 0), then, once every replay is enqueued, the final work and completion events.
+template <typename T>
+el_status feed(el_exec ex, ExecSlot &sl, const Dev<T> &d) {
+    if (sl.tail_done) return EL_OK;
+    el_plan p = sl.plan;
+    const hipStream_t s = sl.stream;
+    const int M = p->g.nsteps, L = p->nrec;
+    const int cap = ex->ahead;
+    while (cap > 0 && sl.count > 0 && hipEventQuery(sl.ring[sl.head]) == hipSuccess) {
+        sl.head = (sl.head + 1) % cap;
+        --sl.count;
+    }
+    while ((sl.full_left > 0 || sl.rem_left) && (cap == 0 || sl.count < cap)) {
+        const bool full = sl.full_left > 0;
+        EX_TRY(hipGraphLaunch(sl.graph[full ? 0 : 1], s), "graph launch");
+        if (full)
+            --sl.full_left;
+        else
+            sl.rem_left = false;
+        if (cap > 0) {
+            EX_TRY(hipEventRecord(sl.ring[(sl.head + sl.count) % cap], s), "record replay end");
+            ++sl.count;
+        }
+    }
+    if (sl.full_left > 0 || sl.rem_left) return EL_OK;
+    if (sl.op == EL_OP_FORWARD)
+        EX_TRY(launch_gather(d, p->rec, static_cast<double *>(sl.out) + (size_t)(M - 1) * L, s), "gather");
+    if (p->fluid_path && p->fast_tiles > 0) EX_TRY(launch_fluid_fill(d, p->tiles, s), "fluid fill");
+    if (sl.op == EL_OP_ADJOINT) EX_TRY(launch_extract(d, static_cast<T *>(sl.out), s), "extract");
+    EX_TRY(hipEventRecord(p->done, s), "record plan completion");
+    EX_TRY(hipEventRecord(sl.done, s), "record slot completion");
+    sl.tail_done = true;
+    return EL_OK;
+}
+
+el_status feed_slot(el_exec ex, ExecSlot &sl) {
+    if (!sl.busy || sl.tail_done) return EL_OK;
+    return sl.plan->g.precision == EL_F64 ? feed(ex, sl, sl.plan->dd) : feed(ex, sl, sl.plan->df);
+}
+
 template <typename T>
 el_status start_op(el_exec ex, ExecSlot &sl, el_plan p, const Dev<T> &d, int op, const void *in, void *out,
                    hipStream_t after) {
@@ -116,15 +171,14 @@ el_status start_op(el_exec ex, ExecSlot &sl, el_plan p, const Dev<T> &d, int op,
         el_status st = capture(p, d, op, rem, traces, ctr, s, &sl.graph[1]);
         if (st != EL_OK) return st;
     }
-    for (int c = 0; c < nfull; ++c) EX_TRY(hipGraphLaunch(sl.graph[0], s), "graph launch");
-    if (rem > 0) EX_TRY(hipGraphLaunch(sl.graph[1], s), "graph launch");
-    if (op == EL_OP_FORWARD)
-        EX_TRY(launch_gather(d, p->rec, static_cast<double *>(out) + (size_t)(M - 1) * L, s), "gather");
-    if (p->fluid_path && p->fast_tiles > 0) EX_TRY(launch_fluid_fill(d, p->tiles, s), "fluid fill");
-    if (op == EL_OP_ADJOINT) EX_TRY(launch_extract(d, static_cast<T *>(out), s), "extract");
-    EX_TRY(hipEventRecord(p->done, s), "record plan completion");
-    EX_TRY(hipEventRecord(sl.done, s), "record slot completion");
-    return EL_OK;
+    sl.op = op;
+    sl.in = in;
+    sl.out = out;
+    sl.full_left = nfull;
+    sl.rem_left = rem > 0;
+    sl.tail_done = false;
+    sl.head = sl.count = 0;
+    return feed<T>(ex, sl, d);
 }
 
 void release(ExecSlot &sl) {
@@ -135,6 +189,21 @@ void release(ExecSlot &sl) {
         }
     sl.plan = nullptr;
     sl.busy = false;
+    sl.tail_done = true;
+    sl.full_left = 0;
+    sl.rem_left = false;
+    sl.head = sl.count = 0;
+}
+
+// Enqueue the rest of a slot's operation and wait for it.
+el_status drain(el_exec ex, ExecSlot &sl) {
+    while (sl.busy && !sl.tail_done) {
+        if (sl.count > 0) EX_TRY(hipEventSynchronize(sl.ring[sl.head]), "wait for a replay");
+        el_status st = feed_slot(ex, sl);
+        if (st != EL_OK) return st;
+    }
+    if (sl.busy) EX_TRY(hipEventSynchronize(sl.done), "wait");
+    return EL_OK;
 }
 
 el_status check_exec(el_exec ex, int slot) {
@@ -176,8 +245,10 @@ el_status el_exec_create(el_exec *out, int32_t max_slots, int32_t chunk_steps) {
 el_status el_exec_destroy(el_exec ex) {
     if (!ex) return EL_OK;
     for (auto &sl : ex->slots) {
-        if (sl.busy && sl.done) (void)hipEventSynchronize(sl.done);
+        if (sl.busy) (void)drain(ex, sl);
         release(sl);
+        for (auto &e : sl.ring) (void)hipEventDestroy(e);
+        sl.ring.clear();
         if (sl.done) (void)hipEventDestroy(sl.done);
         if (sl.ready) (void)hipEventDestroy(sl.ready);
         if (sl.stream) (void)hipStreamDestroy(sl.stream);
@@ -229,6 +300,12 @@ el_status el_exec_poll(el_exec ex, int32_t slot, int32_t *done) {
         *done = 1;
         return EL_OK;
     }
+    st = feed_slot(ex, sl);
+    if (st != EL_OK) return st;
+    if (!sl.tail_done) {
+        *done = 0;
+        return EL_OK;
+    }
     const hipError_t e = hipEventQuery(sl.done);
     if (e == hipErrorNotReady) {
         *done = 0;
@@ -245,8 +322,35 @@ el_status el_exec_wait(el_exec ex, int32_t slot) {
     if (st != EL_OK) return st;
     ExecSlot &sl = ex->slots[slot];
     if (!sl.busy) return EL_OK;
-    EX_TRY(hipEventSynchronize(sl.done), "wait");
+    st = drain(ex, sl);
+    if (st != EL_OK) return st;
     release(sl);
+    return EL_OK;
+}
+
+el_status el_exec_pump(el_exec ex) {
+    if (!ex) return el::set_error(EL_EINVAL, "executor is NULL");
+    for (int q = 0; q < (int)ex->slots.size(); ++q) {
+        el_status st = check_exec(ex, q);
+        if (st != EL_OK) return st;
+        st = feed_slot(ex, ex->slots[q]);
+        if (st != EL_OK) return st;
+    }
+    return EL_OK;
+}
+
+el_status el_exec_set_ahead(el_exec ex, int32_t replays) {
+    if (!ex) return el::set_error(EL_EINVAL, "executor is NULL");
+    if (replays < 0 || replays > 1024) return el::set_error(EL_EINVAL, "replays must be in 0..1024");
+    for (auto &sl : ex->slots)
+        if (sl.busy) return el::set_error(EL_EBUSY, "a slot is running an operation");
+    for (auto &sl : ex->slots) {
+        for (auto &e : sl.ring) (void)hipEventDestroy(e);
+        sl.ring.assign(replays, nullptr);
+        for (auto &e : sl.ring) EX_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming), "replay events");
+        sl.head = sl.count = 0;
+    }
+    ex->ahead = replays;
     return EL_OK;
 }
 

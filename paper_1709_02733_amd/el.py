@@ -60,6 +60,7 @@ EXPORTS = ("el_version", "el_status_string", "el_last_error", "el_grid_check", "
            "el_plan_timing",
            "el_plan_kernel_time",
            "el_exec_create", "el_exec_destroy", "el_exec_start", "el_exec_poll", "el_exec_wait", "el_exec_slots",
+           "el_exec_set_ahead", "el_exec_pump",
            "el_group_create", "el_group_destroy", "el_group_add", "el_group_run", "el_group_sync", "el_group_poll",
            "el_group_remove", "el_group_members")
 KERNELS = ("velocity", "stress", "adj_velocity", "adj_stress", "gather", "scatter", "relax")
@@ -126,6 +127,10 @@ def lib():
         L.el_exec_wait.argtypes = [vp, i32]
         L.el_exec_slots.restype = st
         L.el_exec_slots.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
+        L.el_exec_set_ahead.restype = st
+        L.el_exec_set_ahead.argtypes = [vp, i32]
+        L.el_exec_pump.restype = st
+        L.el_exec_pump.argtypes = [vp]
         L.el_group_create.restype = st
         L.el_group_create.argtypes = [ctypes.POINTER(vp), i32, i32]
         L.el_group_destroy.restype = st
@@ -417,9 +422,11 @@ class Executor:
     start() enqueues a whole forward or adjoint application of a plan on a free
     slot and returns the slot; poll()/wait() report completion.  The plan and
     the in/out tensors are kept alive here until the operation has completed.
+    With ahead > 0 each slot keeps at most that many graph replays in flight and
+    poll()/pump()/wait() enqueue the rest as earlier ones finish.
     """
 
-    def __init__(self, max_slots: int = 4, chunk: int = 64, device=None):
+    def __init__(self, max_slots: int = 4, chunk: int = 64, device=None, ahead: int = 0):
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
         h = ctypes.c_void_p(None)
         with torch.cuda.device(self.device):
@@ -428,6 +435,18 @@ class Executor:
         self._lib = lib()
         self.max_slots = int(max_slots)
         self._held = {}
+        if ahead:
+            self.set_ahead(ahead)
+
+    def set_ahead(self, replays: int):
+        with torch.cuda.device(self.device):
+            _check(lib().el_exec_set_ahead(self._h, int(replays)))
+        self.ahead = int(replays)
+
+    def pump(self):
+        """Enqueue what the replay limit allows on every running slot."""
+        with torch.cuda.device(self.device):
+            _check(lib().el_exec_pump(self._h))
 
     def start(self, plan: "Plan", op: int, inp: torch.Tensor, out: torch.Tensor, stream=None) -> int:
         """The operation is ordered after the work enqueued so far on `stream` (default: the

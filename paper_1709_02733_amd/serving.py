@@ -451,7 +451,7 @@ def summarize(reqs) -> dict:
 
 
 def serve_benchmark(rates=(2, 5, 10, 20), count=200, sizes=SIZES, max_slots=8, chunk=64, budget=200e9, seed=0,
-                    modes=("plain", "executor"), per_request_media=True,
+                    modes=("plain", "executor"), per_request_media=True, hybrid_ahead=2,
                     log=lambda *a: print(*a, file=sys.stderr, flush=True)):
     """Plain versus batched serving of the same request streams; one entry per rate, with a
     summary per mode ("plain"; "grouped": el_group; "executor": per-slot graph streams;
@@ -461,12 +461,11 @@ def serve_benchmark(rates=(2, 5, 10, 20), count=200, sizes=SIZES, max_slots=8, c
     wl = Workloads(sizes, per_request_media=per_request_media)
     group = el.Group(max_members=max_slots) if ("grouped" in modes or "hybrid" in modes) else None
     ex = el.Executor(max_slots=min(max_slots, 4), chunk=chunk) if "executor" in modes else None
-    # hybrid: its own executor with two slots for the large requests.  With the group's stream
-    # and the caller's, two executor streams can each have a hardware queue of their own (four
-    # per process); with more, the group's small launches may wait in a queue behind a large
-    # request's graph (measured on 40 requests at 10 req/s: median latency 1.3 s with two
-    # slots, 3.7 and 2.9 s with three and four)
-    ex_h = el.Executor(max_slots=2, chunk=chunk) if "hybrid" in modes else None
+    # hybrid: its own executor with two slots for the large requests, each holding at most
+    # `hybrid_ahead` graph replays in flight.  The group's stream and the executor's share four
+    # hardware queues per process; a large request enqueued whole can put the group's small
+    # launches behind all of its steps, a bounded number of replays only behind those
+    ex_h = el.Executor(max_slots=2, chunk=chunk, ahead=hybrid_ahead) if "hybrid" in modes else None
     runners = {"plain": lambda q: run_plain(q, wl),
                "grouped": lambda q: run_grouped(q, wl, group, budget, max_large=1),
                "executor": lambda q: run_batched(q, wl, ex, budget),
@@ -505,10 +504,12 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--modes", nargs="+", default=["plain", "executor"], choices=["plain", "grouped", "executor", "hybrid"])
     ap.add_argument("--shared-media", action="store_true", help="one medium per size instead of one per request")
+    ap.add_argument("--hybrid-ahead", type=int, default=2,
+                    help="graph replays in flight per executor slot in hybrid mode (0: whole operations)")
     args = ap.parse_args()
     res = serve_benchmark(rates=args.rates, count=args.count, max_slots=args.slots, chunk=args.chunk,
                           budget=args.budget_gb * 1e9, seed=args.seed, modes=tuple(args.modes),
-                          per_request_media=not args.shared_media)
+                          per_request_media=not args.shared_media, hybrid_ahead=args.hybrid_ahead)
     print(json.dumps(res))
 
 

@@ -153,3 +153,43 @@ def test_executor_rejects_when_full(small):
     ex.wait(s1)
     assert ex.slots() == (1, 0)
     ex.close()
+
+
+@pytest.mark.parametrize("ahead", [1, 3])
+def test_executor_replay_limit(small, ahead):
+    """With at most `ahead` graph replays in flight per slot (the rest enqueued by poll,
+    pump and wait as earlier replays finish), concurrent operations give bitwise the
+    results of the same requests run alone; the limit is rejected while a slot runs."""
+    wl, reqs = small
+    ex = el.Executor(max_slots=3, chunk=8, ahead=ahead)
+    with pytest.raises(el.ElError) as ei:
+        ex.set_ahead(-1)
+    assert ei.value.status == el.EL_EINVAL
+    rs = reqs[:3]
+    plans = [wl.plan(r) for r in rs]
+    ios = [wl.io(r) for r in rs]
+    slots = [ex.start(p, r.op, i, o) for p, r, (i, o) in zip(plans, rs, ios)]
+    with pytest.raises(el.ElError) as ei:
+        ex.set_ahead(0)
+    assert ei.value.status == el.EL_EBUSY
+    ex.pump()
+    ex.wait(slots[2])
+    live = set(slots[:2])
+    while live:
+        live = {s for s in live if not ex.poll(s)}
+    assert ex.slots()[1] == 0
+    for r, (_, o) in zip(rs, ios):
+        assert torch.equal(o, _alone(wl, r)), r
+    # a busy slot at close: the rest of its operation is enqueued and waited for
+    r = reqs[3]
+    p, (i, o) = wl.plan(r), wl.io(r)
+    ex.start(p, r.op, i, o)
+    ex.close()
+    torch.cuda.synchronize()
+    assert torch.equal(o, _alone(wl, r))
+    # run_batched drives a limited executor through poll alone
+    ex = el.Executor(max_slots=3, chunk=16, ahead=ahead)
+    out = SV.run_batched(SV.clone_requests(reqs), wl, ex, budget_bytes=200e9)
+    for q in out:
+        assert torch.equal(q.output, _alone(wl, q)), q.rid
+    ex.close()

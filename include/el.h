@@ -396,7 +396,7 @@ typedef struct el_exec_ *el_exec;
 /* Create an executor on the current device.  max_slots in 1..64, chunk_steps >= 1. */
 el_status el_exec_create(el_exec *out, int32_t max_slots, int32_t chunk_steps);
 
-/* Wait for every slot, then release the executor. */
+/* Enqueue what a replay limit has held back, wait for every slot, then release the executor. */
 el_status el_exec_destroy(el_exec ex);
 
 /*

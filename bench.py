@@ -350,7 +350,7 @@ def main():
         fk = planf.kernel_times()
         ff_ms, fa_ms = f0.elapsed_time(f1), f1.elapsed_time(f2)
         n_r, ms_r = fk.get("relax", (0, 0.0))
-        rb = bytemodel.relax_bytes(rcells, rpoints, len(scf.mechanisms), 4)
+        rb = bytemodel.relax_bytes(rpoints, len(scf.mechanisms), 4)
         r_us = ms_r / max(n_r, 1) * 1e3
         freqdep = {"workload": f"{scf.name}: the skull's absorption as relaxation mechanisms "
                                f"{[(round(o / 2 / 3.141592653589793 / 1e6, 3), w) for o, w in scf.mechanisms]} "

@@ -80,8 +80,8 @@ def step_bytes(op: str, nx, ny, nz, npml, nrec, es=4, fluid_cells: int = 0, flui
                             uniform_cells) for k in ks)
 
 
-def relax_bytes(cells: int, points: int, nmech: int, es: int = 4) -> float:
-    """Algorithmic bytes of one relaxation launch (frequency-dependent absorption): the
-    strength map alpha_r read once per cell of the tiles it visits, and per velocity point with
-    beta > 0 (el_plan_relaxation) the velocity and the nmech memory variables read and written."""
-    return float(cells * es + points * (2 + 2 * nmech) * es)
+def relax_bytes(points: int, nmech: int, es: int = 4) -> float:
+    """Algorithmic bytes of one relaxation launch (frequency-dependent absorption): per velocity
+    point with beta > 0 (el_plan_relaxation) its strength beta read, and the velocity and the
+    nmech memory variables read and written.  Elsewhere the sub-update is the identity."""
+    return float(points * (3 + 2 * nmech) * es)

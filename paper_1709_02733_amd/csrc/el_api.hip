@@ -110,8 +110,11 @@ bool layout(const el_grid &g, int nrec, Layout *L) {
         L->relax_map = nm > 0 ? take(N * es) : 0;
         L->relax_flag = nm > 0 ? take((size_t)t.ntiles) : 0;
         L->relax_count = nm > 0 ? take((size_t)t.ntiles * sizeof(int)) : 0;
-        L->relax_order = nm > 0 ? take((size_t)8 * t.per * sizeof(int)) : 0;
-        L->relax_zeta = nm > 0 ? take((size_t)t.ntiles * 3 * nm * t.zc * kTileX * kTileY * es) : 0;
+        const size_t cap = (size_t)t.ntiles * 3 * t.zc * kTileX * kTileY;   // points at most
+        L->relax_off = nm > 0 ? take((size_t)t.ntiles * sizeof(long long)) : 0;
+        L->relax_pts = nm > 0 ? take(cap * sizeof(unsigned)) : 0;
+        L->relax_beta = nm > 0 ? take(cap * es) : 0;
+        L->relax_zeta = nm > 0 ? take(cap * nm * es) : 0;
     }
     L->partial = take(kStats * kDotBlocks * 8);
     L->total = off;
@@ -358,9 +361,12 @@ void bind_relax(Relax<T> &r, el_plan_ *p) {
     }
     if (rx.nmech > 0) {
         r.ar = reinterpret_cast<T *>(p->ws + p->L.relax_map);
-        r.zeta = reinterpret_cast<T *>(p->ws + p->L.relax_zeta);
         r.flag = reinterpret_cast<unsigned char *>(p->ws + p->L.relax_flag);
         r.count = reinterpret_cast<int *>(p->ws + p->L.relax_count);
+        r.off = reinterpret_cast<long long *>(p->ws + p->L.relax_off);
+        r.pts = reinterpret_cast<unsigned *>(p->ws + p->L.relax_pts);
+        r.beta = reinterpret_cast<T *>(p->ws + p->L.relax_beta);
+        r.zeta = reinterpret_cast<T *>(p->ws + p->L.relax_zeta);
     }
 }
 
@@ -704,33 +710,29 @@ el_status el_plan_create(el_plan *out, const el_grid *grid, const float *lam, co
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         if (e != hipSuccess) return bail(hip_fail(e, "relaxation tiles"));
         const Tiles &t = p->tiles;
+        // the point list: the points of tile q start at roff[q] (tiles in index order)
+        std::vector<long long> roff(t.ntiles, 0);
+        long long npts = 0;
         for (int q = 0; q < t.ntiles; ++q) {
+            roff[q] = npts;
             if (!rflag[q]) continue;
             const int bx = q % t.ntx, r = q / t.ntx, by = r % t.nty, bz = r / t.nty;
             p->relax_tiles += 1;
             p->relax_points += rcount[q];
+            npts += rcount[q];
             p->relax_cells += (long long)std::min(kTileX, grid->nx - bx * kTileX) * std::min(kTileY, grid->ny - by * kTileY) *
                               std::min(t.zc, grid->nz - bz * t.zc);
         }
-        // launch order of the relaxation: the flagged tiles of XCD x (in z-major order) at blocks
-        // x, x + 8, x + 16, ..., padded with -1
-        std::vector<std::vector<int>> per_xcd(8);
-        for (int q = 0; q < t.ntiles; ++q)
-            if (rflag[q]) per_xcd[tile_xcd(t, q)].push_back(q);
-        size_t most = 0;
-        for (auto &v : per_xcd) most = std::max(most, v.size());
-        std::vector<int> rorder(8 * most, -1);
-        for (int x = 0; x < 8; ++x)
-            for (size_t n = 0; n < per_xcd[x].size(); ++n) rorder[8 * n + x] = per_xcd[x][n];
-        int *dst = reinterpret_cast<int *>(p->ws + L.relax_order);
-        if (!rorder.empty()) {
-            e = hipMemcpyAsync(dst, rorder.data(), rorder.size() * sizeof(int), hipMemcpyHostToDevice, s);
-            if (e == hipSuccess) e = hipStreamSynchronize(s);
-            if (e != hipSuccess) return bail(hip_fail(e, "relaxation order"));
-        }
-        p->rf.order = dst;
-        p->rd.order = dst;
-        p->rf.nblocks = p->rd.nblocks = (int)rorder.size();
+        // a point keeps its element index in 30 bits
+        const long long elements = (long long)(grid->precision == EL_F64 ? p->dd.plane : p->df.plane) * (grid->nz + 4);
+        if (elements > (long long)kRelaxElemMask + 1)
+            return bail(fail(EL_EINVAL, "relaxation needs a padded grid of at most 2^30 elements (%lld)", elements));
+        e = hipMemcpyAsync(p->ws + L.relax_off, roff.data(), roff.size() * sizeof(long long), hipMemcpyHostToDevice, s);
+        p->rf.npts = p->rd.npts = npts;
+        if (e == hipSuccess)
+            e = grid->precision == EL_F64 ? launch_relax_compact(p->dd, t, p->rd, s) : launch_relax_compact(p->df, t, p->rf, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return bail(hip_fail(e, "relaxation point list"));
     }
     st = upload_receivers(p, rec, s);
     if (st != EL_OK) return bail(st);

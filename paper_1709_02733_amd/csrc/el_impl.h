@@ -152,14 +152,19 @@ struct Relax {
     T w[EL_MAX_MECH];        // weights
     T c[EL_MAX_MECH];        // exp(-omega_l dt)
     const T *ar;             // strength alpha_r, a padded cell map (edge-replicated like the others)
-    T *zeta;                 // [tile][l][component][plane of the chunk][row][column]: kTileX * kTileY
-                             // * zc values per (tile, l, component)
-    const unsigned char *flag;   // per tile: 1 if some velocity point of it has beta > 0
+    const unsigned char *flag;   // per tile: 1 if some velocity point of it has beta > 0 (set-up)
     int *count;              // per tile: its (cell, component) velocity points with beta > 0 (set-up)
-    const int *order;        // flagged tile of each block of the relaxation launch (-1: none);
-                             // block b runs on XCD b mod 8, which holds the tile (tile_xcd)
-    int nblocks;             // blocks of the relaxation launch
+    long long *off;          // per tile: index of its first point in pts (set-up)
+    // the velocity points with beta > 0, tile by tile, within a tile by component, then plane,
+    // row, column: the padded element index with the component in bits 30-31, beta, and the
+    // memory variables [l][point]
+    unsigned *pts;
+    T *beta;
+    T *zeta;
+    long long npts;
 };
+
+constexpr unsigned kRelaxElemMask = (1u << 30) - 1;
 
 // Receiver tables (cell offsets are padded element indices).
 struct Rec {
@@ -279,7 +284,9 @@ struct Layout {
     size_t relax_map;        // alpha_r (padded cell map), with relaxation mechanisms only
     size_t relax_flag;       // per tile: relaxation applies
     size_t relax_count;      // per tile: velocity points with beta > 0 (int)
-    size_t relax_order;      // flagged tile of each block of the relaxation launch (int)
+    size_t relax_off;        // per tile: first point of the tile in the point list (long long)
+    size_t relax_pts;        // point list: element index and component (unsigned), at most 3 per cell
+    size_t relax_beta;       // beta of each point
     size_t relax_zeta;       // memory variables of the relaxation mechanisms (Relax::zeta)
     size_t total;
 };
@@ -345,6 +352,8 @@ hipError_t launch_relax_stats(const float *ar, int nx, int ny, int nz, int margi
                               hipStream_t s);
 template <typename T> hipError_t launch_relax_setup(const Dev<T> &d, const Tiles &tl, const float *ar_cells,
                                                     const Relax<T> &r, hipStream_t s);
+template <typename T> hipError_t launch_relax_compact(const Dev<T> &d, const Tiles &tl, const Relax<T> &r,
+                                                      hipStream_t s);
 template <typename T> hipError_t launch_relax_zero(const Tiles &tl, const Relax<T> &r, hipStream_t s);
 template <typename T> hipError_t launch_relax(const Dev<T> &d, const Tiles &tl, const Relax<T> &r, bool adjoint,
                                               hipStream_t s);

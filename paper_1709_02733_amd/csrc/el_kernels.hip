@@ -514,130 +514,143 @@ hipError_t launch_relax_setup(const Dev<T> &d, const Tiles &tl, const float *ar_
     return hipGetLastError();
 }
 
-// Memory variables of the flagged tiles set to zero (initial state of an operation).
+// The point list (Relax::pts): block q writes the points of tile q from off[q] on, in the order
+// component, plane, row, column, each with its beta, by the same test as k_relax_flags; a
+// prefix sum over the block places each lane's point.  Exactly count[q] points are written.
 template <typename T>
-__global__ __launch_bounds__(256) void k_relax_zero(Tiles tl, Relax<T> r) {
+__global__ __launch_bounds__(256) void k_relax_compact(Dev<T> d, Tiles tl, Relax<T> r) {
     const int q = blockIdx.x;
     if (q >= tl.ntiles || !r.flag[q]) return;
-    const long long per = (long long)3 * r.L * tl.zc * kTileX * kTileY;
-    T *z = r.zeta + (long long)q * per;
-    for (long long e = threadIdx.x; e < per; e += blockDim.x) z[e] = T(0);
+    const int bx = q % tl.ntx, rr = q / tl.ntx, by = rr % tl.nty, bz = rr / tl.nty;
+    const int x0 = bx * kTileX, y0 = by * kTileY, z0 = bz * tl.zc;
+    const int w = min(kTileX, d.nx - x0), hgt = min(kTileY, d.ny - y0), dep = min(tl.zc, d.nz - z0);
+    const int ncell = w * hgt * dep;
+    const long long base = r.off[q];
+    const int limit = r.count[q];
+    const long long stride[3] = {1, d.px, d.plane};
+    __shared__ int wave_n[4];
+    const int lane = (int)threadIdx.x & 63, wave = (int)threadIdx.x >> 6;
+    int done = 0;
+    for (int c = 0; c < 3; ++c) {
+        for (int e0 = 0; e0 < ncell; e0 += 256) {
+            const int e = e0 + (int)threadIdx.x;
+            bool on = false;
+            long long el = 0;
+            T beta = T(0);
+            if (e < ncell) {
+                const int xx = x0 + e % w, rem = e / w;
+                const int yy = y0 + rem % hgt, zz = z0 + rem / hgt;
+                el = (long long)(zz + 2) * d.plane + (long long)yy * d.px + xx;
+                beta = T(0.5) * (r.ar[el] + r.ar[el + stride[c]]);
+                on = beta > T(0);
+            }
+            const unsigned long long m = __ballot(on);
+            const int before = __popcll(m & ((1ull << lane) - 1ull));
+            if (lane == 0) wave_n[wave] = __popcll(m);
+            __syncthreads();
+            int pos = done + before;
+            int total = 0;
+            for (int v = 0; v < 4; ++v) {
+                if (v < wave) pos += wave_n[v];
+                total += wave_n[v];
+            }
+            if (on && pos < limit) {
+                r.pts[base + pos] = (unsigned)el | ((unsigned)c << 30);
+                r.beta[base + pos] = beta;
+            }
+            done += total;
+            __syncthreads();
+        }
+    }
+    // the flags kernel counted these points with the same test, so nothing is left; were any
+    // left, they become points with beta = 0 (R the identity) on the tile's first cell
+    for (int pos = done + (int)threadIdx.x; pos < limit; pos += 256) {
+        r.pts[base + pos] = (unsigned)((long long)(z0 + 2) * d.plane + (long long)y0 * d.px + x0);
+        r.beta[base + pos] = T(0);
+    }
 }
 
 template <typename T>
-hipError_t launch_relax_zero(const Tiles &tl, const Relax<T> &r, hipStream_t s) {
+hipError_t launch_relax_compact(const Dev<T> &d, const Tiles &tl, const Relax<T> &r, hipStream_t s) {
     if (r.L == 0 || tl.ntiles == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_relax_zero<T>, dim3(tl.ntiles), dim3(256), 0, s, tl, r);
+    hipLaunchKernelGGL(k_relax_compact<T>, dim3(tl.ntiles), dim3(256), 0, s, d, tl, r);
     return hipGetLastError();
 }
 
-// The sub-update R (ADJ: R^T) on the flagged tile of each block (Relax::order).  The strengths
-// of a plane (the cell's and its +x, +y, +z neighbours') are loaded two planes ahead, the
-// velocities and memory variables one plane ahead and only for the components with beta > 0
-// (most cells of a flagged tile have none: the loads are masked off per lane), so the loads
-// of two planes are in flight while one is computed.
+// Memory variables set to zero (initial state of an operation).
+template <typename T>
+__global__ __launch_bounds__(256) void k_relax_zero(Relax<T> r) {
+    const long long n = r.npts * r.L;
+    for (long long e = blockIdx.x * 256LL + threadIdx.x; e < n; e += (long long)gridDim.x * 256) r.zeta[e] = T(0);
+}
+
+template <typename T>
+hipError_t launch_relax_zero(const Tiles &, const Relax<T> &r, hipStream_t s) {
+    if (r.L == 0 || r.npts == 0) return hipSuccess;
+    const long long n = r.npts * r.L;
+    const long long blocks = std::min<long long>((n + 255) / 256, 8192);
+    hipLaunchKernelGGL(k_relax_zero<T>, dim3((unsigned)blocks), dim3(256), 0, s, r);
+    return hipGetLastError();
+}
+
+// The sub-update R (ADJ: R^T) at one velocity point with beta > 0 per lane (elsewhere R is the
+// identity), the points and their memory variables read in list order.
 template <typename T, bool ADJ, int L>
-__global__ __launch_bounds__(256) void k_relax(Dev<T> d, Tiles tl, Relax<T> r) {
-    const int q = r.order[blockIdx.x];
-    if (q < 0) return;
-    const int bx = q % tl.ntx, rr = q / tl.ntx, by = rr % tl.nty, bz = rr / tl.nty;
-    const int col = (int)threadIdx.x % kTileX, row = (int)threadIdx.x / kTileX;
-    const int i = bx * kTileX + col, j = by * kTileY + row, z0 = bz * tl.zc;
-    if (i >= d.nx || j >= d.ny) return;
-    const int z1 = min(z0 + tl.zc, d.nz);
-    const long long per_c = (long long)tl.zc * kTileX * kTileY;       // one (l, component) of a tile
-    T *zt = r.zeta + (long long)q * 3 * L * per_c + (long long)row * kTileX + col;
+__global__ __launch_bounds__(256) void k_relax(Dev<T> d, Relax<T> r) {
+    const long long p = blockIdx.x * 256LL + threadIdx.x;
+    if (p >= r.npts) return;
+    const unsigned pk = r.pts[p];
+    const int c = (int)(pk >> 30);
+    const long long e = pk & kRelaxElemMask;
+    const T beta = r.beta[p];
+    T z[L];
+#pragma unroll
+    for (int l = 0; l < L; ++l) z[l] = r.zeta[l * r.npts + p];
+    T *u = c == 0 ? d.f[U1] : (c == 1 ? d.f[U2] : d.f[U3]);
+    const T uo = u[e];
     const T dt = d.dt;
-    struct Coef {
-        T a[4];          // alpha_r at the cell and at its +x, +y, +z neighbours
-    };
-    struct Plane {
-        T u[3];
-        T z[L][3];
-    };
-    auto load_coef = [&](Coef &p, int k) {
-        const long long e = (long long)(k + 2) * d.plane + (long long)j * d.px + i;
-        p.a[0] = r.ar[e];
-        p.a[1] = r.ar[e + 1];
-        p.a[2] = r.ar[e + d.px];
-        p.a[3] = r.ar[e + d.plane];
-    };
-    auto load = [&](Plane &p, const Coef &cf, int k) {
-        const long long e = (long long)(k + 2) * d.plane + (long long)j * d.px + i;
-        const long long zk = (long long)(k - z0) * kTileX * kTileY;
+    T bl[L];
+    T B = T(0);
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            const bool on = cf.a[0] + cf.a[1 + c] > T(0);
-            p.u[c] = on ? d.f[U1 + c][e] : T(0);
+    for (int l = 0; l < L; ++l) {
+        bl[l] = r.w[l] * beta;
+        B += bl[l];
+    }
+    const T a = T(1) / (T(1) + dt * B);
+    if (!ADJ) {
+        T acc = uo;
 #pragma unroll
-            for (int l = 0; l < L; ++l) p.z[l][c] = on ? zt[((long long)l * 3 + c) * per_c + zk] : T(0);
-        }
-    };
-    Coef c_cur, c_nxt{}, c_nn{};
-    Plane cur, nxt;
-    load_coef(c_cur, z0);
-    if (z0 + 1 < z1) load_coef(c_nxt, z0 + 1);
-    load(cur, c_cur, z0);
-    for (int k = z0; k < z1; ++k) {
-        if (k + 2 < z1) load_coef(c_nn, k + 2);
-        if (k + 1 < z1) load(nxt, c_nxt, k + 1);
-        __builtin_amdgcn_sched_barrier(0);
-        const long long e = (long long)(k + 2) * d.plane + (long long)j * d.px + i;
-        const long long zk = (long long)(k - z0) * kTileX * kTileY;
+        for (int l = 0; l < L; ++l) acc += dt * bl[l] * z[l];
+        const T un = acc * a;
+        u[e] = un;
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            const T beta = T(0.5) * (c_cur.a[0] + c_cur.a[1 + c]);
-            if (beta > T(0)) {                     // else R is the identity (and R^T, with z = 0)
-                T bl[L];
-                T B = T(0);
+        for (int l = 0; l < L; ++l) r.zeta[l * r.npts + p] = r.c[l] * z[l] + (T(1) - r.c[l]) * un;
+    } else {
+        T sum = uo;
 #pragma unroll
-                for (int l = 0; l < L; ++l) {
-                    bl[l] = r.w[l] * beta;
-                    B += bl[l];
-                }
-                const T a = T(1) / (T(1) + dt * B);
-                if (!ADJ) {
-                    T acc = cur.u[c];
+        for (int l = 0; l < L; ++l) sum += (T(1) - r.c[l]) * z[l];
+        u[e] = a * sum;
 #pragma unroll
-                    for (int l = 0; l < L; ++l) acc += dt * bl[l] * cur.z[l][c];
-                    const T un = acc * a;
-                    d.f[U1 + c][e] = un;
-#pragma unroll
-                    for (int l = 0; l < L; ++l)
-                        zt[((long long)l * 3 + c) * per_c + zk] = r.c[l] * cur.z[l][c] + (T(1) - r.c[l]) * un;
-                } else {
-                    T sum = cur.u[c];
-#pragma unroll
-                    for (int l = 0; l < L; ++l) sum += (T(1) - r.c[l]) * cur.z[l][c];
-                    d.f[U1 + c][e] = a * sum;
-#pragma unroll
-                    for (int l = 0; l < L; ++l)
-                        zt[((long long)l * 3 + c) * per_c + zk] = dt * bl[l] * a * sum + r.c[l] * cur.z[l][c];
-                }
-            }
-        }
-        cur = nxt;
-        c_cur = c_nxt;
-        c_nxt = c_nn;
+        for (int l = 0; l < L; ++l) r.zeta[l * r.npts + p] = dt * bl[l] * a * sum + r.c[l] * z[l];
     }
 }
 
 template <typename T, bool ADJ>
-hipError_t launch_relax_l(const Dev<T> &d, const Tiles &tl, const Relax<T> &r, hipStream_t s) {
-    const dim3 g(r.nblocks), b(256);
+hipError_t launch_relax_l(const Dev<T> &d, const Relax<T> &r, hipStream_t s) {
+    const dim3 g((unsigned)((r.npts + 255) / 256)), b(256);
     switch (r.L) {
-        case 1: hipLaunchKernelGGL((k_relax<T, ADJ, 1>), g, b, 0, s, d, tl, r); break;
-        case 2: hipLaunchKernelGGL((k_relax<T, ADJ, 2>), g, b, 0, s, d, tl, r); break;
-        case 3: hipLaunchKernelGGL((k_relax<T, ADJ, 3>), g, b, 0, s, d, tl, r); break;
-        default: hipLaunchKernelGGL((k_relax<T, ADJ, 4>), g, b, 0, s, d, tl, r); break;
+        case 1: hipLaunchKernelGGL((k_relax<T, ADJ, 1>), g, b, 0, s, d, r); break;
+        case 2: hipLaunchKernelGGL((k_relax<T, ADJ, 2>), g, b, 0, s, d, r); break;
+        case 3: hipLaunchKernelGGL((k_relax<T, ADJ, 3>), g, b, 0, s, d, r); break;
+        default: hipLaunchKernelGGL((k_relax<T, ADJ, 4>), g, b, 0, s, d, r); break;
     }
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_relax(const Dev<T> &d, const Tiles &tl, const Relax<T> &r, bool adjoint, hipStream_t s) {
-    if (r.L == 0 || r.nblocks == 0) return hipSuccess;
-    return adjoint ? launch_relax_l<T, true>(d, tl, r, s) : launch_relax_l<T, false>(d, tl, r, s);
+hipError_t launch_relax(const Dev<T> &d, const Tiles &, const Relax<T> &r, bool adjoint, hipStream_t s) {
+    if (r.L == 0 || r.npts == 0) return hipSuccess;
+    return adjoint ? launch_relax_l<T, true>(d, r, s) : launch_relax_l<T, false>(d, r, s);
 }
 
 // ------------------------------------------------------ inner products
@@ -695,6 +708,7 @@ hipError_t launch_dot(const T *a, const T *b, long long n, double *partial, doub
     template hipError_t launch_relax_setup<T>(const Dev<T> &, const Tiles &, const float *, const Relax<T> &,      \
                                               hipStream_t);                                                        \
     template hipError_t launch_relax_zero<T>(const Tiles &, const Relax<T> &, hipStream_t);                         \
+    template hipError_t launch_relax_compact<T>(const Dev<T> &, const Tiles &, const Relax<T> &, hipStream_t);      \
     template hipError_t launch_relax<T>(const Dev<T> &, const Tiles &, const Relax<T> &, bool, hipStream_t);
 
 EL_INST(float)

@@ -422,7 +422,8 @@ el_status el_exec_slots(el_exec ex, int32_t *total, int32_t *busy);
  * an operation whole at el_exec_start; r in 1..1024 enqueues r replays there and
  * the rest from el_exec_poll / el_exec_pump / el_exec_wait as earlier replays
  * complete, which bounds how much of one slot's work is queued ahead of other
- * streams.  EL_EBUSY while a slot is running; EL_EINVAL for r outside 0..1024.
+ * streams.  EL_EBUSY while a slot is running; EL_EINVAL for r outside 0..1024;
+ * EL_EDEVICE if the replay events cannot be created (the executor is then unlimited).
  */
 el_status el_exec_set_ahead(el_exec ex, int32_t replays);
 

@@ -344,11 +344,19 @@ el_status el_exec_set_ahead(el_exec ex, int32_t replays) {
     if (replays < 0 || replays > 1024) return el::set_error(EL_EINVAL, "replays must be in 0..1024");
     for (auto &sl : ex->slots)
         if (sl.busy) return el::set_error(EL_EBUSY, "a slot is running an operation");
+    // no limit until every slot has its events (a failure leaves the executor unlimited)
+    ex->ahead = 0;
     for (auto &sl : ex->slots) {
         for (auto &e : sl.ring) (void)hipEventDestroy(e);
-        sl.ring.assign(replays, nullptr);
-        for (auto &e : sl.ring) EX_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming), "replay events");
+        sl.ring.clear();
         sl.head = sl.count = 0;
+    }
+    for (auto &sl : ex->slots) {
+        for (int n = 0; n < replays; ++n) {
+            hipEvent_t e = nullptr;
+            EX_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming), "replay events");
+            sl.ring.push_back(e);
+        }
     }
     ex->ahead = replays;
     return EL_OK;

@@ -83,6 +83,46 @@ def test_velocity_update_exact_for_cubic_stress():
         assert err < 1e-11, (i, err)
 
 
+def test_velocity_update_at_the_upper_face_by_hand():
+    """The velocity update (Sec. 2.2, eq. it) at the last two u^1 points along x, worked
+    out by hand: rho and alpha at a velocity point are the mean of its two cells with the
+    upper cell replicated past the last index (so the last point takes the last cell's
+    values), and the 4th-order difference D+ (eq. derivative) reads zero beyond the grid.
+    Only sigma11 is nonzero, so the update of u^1 is (1 - dt alpha) u + dt/rho D+ sigma11."""
+    rng = np.random.default_rng(5)
+    nx, ny, nz = 9, 5, 4
+    shp = (nz, ny, nx)
+    dx, dt = 1e-3, 2e-8
+    # media exact in float32, the precision the operator takes them in
+    rho = rng.uniform(900.0, 2100.0, shp).astype(np.float32).astype(np.float64)
+    alpha = rng.uniform(0.0, 5e4, shp).astype(np.float32).astype(np.float64)
+    sc = S.random_scenario((nx, ny, nz), seed=0, npml=0, nrec=1)
+    m = _model(sc, lam=np.full(shp, 2.2e9), mu=np.zeros(shp), rho=rho, alpha=alpha, npml=0, dx=dx, dt=dt)
+    dt, dx = m.g.dt, m.g.dx
+    v = np.zeros(27 * m.N)
+    sv = m.state_views(v)
+    s11 = rng.uniform(-1e5, 1e5, shp)
+    u1 = rng.uniform(-1.0, 1.0, shp)
+    sv["sig"][0][...] = s11
+    sv["u"][0][...] = u1
+    m.step(v)
+    got = sv["u"][0]
+    for k in range(nz):
+        for j in range(ny):
+            a, b, c = s11[k, j, nx - 3], s11[k, j, nx - 2], s11[k, j, nx - 1]
+            # i = nx - 1: taps i+1, i+2 outside the grid; rho, alpha of the last cell alone
+            d_last = (9.0 / 8.0 * (0.0 - c) - 1.0 / 24.0 * (0.0 - b)) / dx
+            r_last, a_last = rho[k, j, nx - 1], alpha[k, j, nx - 1]
+            want = (1.0 - dt * a_last) * u1[k, j, nx - 1] + dt / r_last * d_last
+            assert got[k, j, nx - 1] == pytest.approx(want, rel=1e-13, abs=1e-15)
+            # i = nx - 2: tap i+2 outside the grid; the mean of the last two cells
+            d_prev = (9.0 / 8.0 * (c - b) - 1.0 / 24.0 * (0.0 - a)) / dx
+            r_prev = 0.5 * (rho[k, j, nx - 2] + rho[k, j, nx - 1])
+            a_prev = 0.5 * (alpha[k, j, nx - 2] + alpha[k, j, nx - 1])
+            want = (1.0 - dt * a_prev) * u1[k, j, nx - 2] + dt / r_prev * d_prev
+            assert got[k, j, nx - 2] == pytest.approx(want, rel=1e-13, abs=1e-15)
+
+
 def test_stress_update_exact_for_cubic_velocity():
     """sigma_{m+1} = sigma_m + Psi u_{m+1/2} (Sec. 2.2, eq. Operatordef, eq. it).
 

@@ -63,8 +63,7 @@
  * R^T, the transpose of the same matrix, at the mirrored place.  The memory
  * variables zeta_l extend the state after the paper's 27N entries.
  *
- * Parity unpinned: the C-PML constants (d0, R, beta, f0) and the zero rule
- * of the harmonic mean of mu (0 when one of its cells is 0) are conventions
+ * Parity unpinned: the C-PML constants (d0, R, beta, f0) are a convention
  * that no value of the paper fixes; the tests hold the oracle to their stated
  * form only.
  */

@@ -180,6 +180,51 @@ def test_stress_update_exact_for_cubic_velocity():
         assert err < 1e-6, ("shear", i, j, off, err)
 
 
+def test_zero_shear_modulus_is_the_limit_of_the_harmonic_mean():
+    """mu at a shear point is the harmonic mean of its four cells (Sec. 2.2); with one cell
+    at mu = 0 (fluid) it is 0, which is the limit of 4 / sum(1/mu) as that modulus goes to
+    0.  So a cell at mu = 1e-30 gives the same state as mu = 0 up to rounding, and with
+    mu = 0 the shear stresses at the four shear points around that cell in the plane of
+    each shear component keep their values.  A rule that averaged only the nonzero cells
+    would update them and break the continuity."""
+    rng = np.random.default_rng(21)
+    nx, ny, nz = 10, 9, 8
+    shp = (nz, ny, nx)
+    lam = rng.uniform(2e9, 4e9, shp).astype(np.float32).astype(np.float64)
+    mu = rng.uniform(0.5e9, 1.5e9, shp).astype(np.float32).astype(np.float64)
+    k0, j0, i0 = 4, 4, 5
+    sc = S.random_scenario((nx, ny, nz), seed=0, npml=0, nrec=1)
+    states = []
+    for eps in (0.0, 1e-30):
+        mu_e = mu.copy()
+        mu_e[k0, j0, i0] = eps
+        m = _model(sc, lam=lam, mu=mu_e, rho=np.full(shp, 1800.0), alpha=np.zeros(shp), npml=0, dx=1e-3, dt=1e-7)
+        v = np.zeros(27 * m.N)
+        sv = m.state_views(v)
+        r = np.random.default_rng(22)
+        for a in range(6):
+            sv["sig"][a][...] = r.uniform(-1e5, 1e5, shp)
+        for i in range(3):
+            sv["u"][i][...] = r.uniform(-1.0, 1.0, shp)
+        before = [sv["sig"][a].copy() for a in range(6)]
+        m.step(v)
+        if eps == 0.0:
+            # sigma12 at (i+1/2, j+1/2, k) over cells i..i+1, j..j+1; sigma13 over i, k;
+            # sigma23 over j, k (index (i, j, k) holds the point above-right of its cell)
+            touch = {VOIGT[(0, 1)]: [(k0, jj, ii) for jj in (j0 - 1, j0) for ii in (i0 - 1, i0)],
+                     VOIGT[(0, 2)]: [(kk, j0, ii) for kk in (k0 - 1, k0) for ii in (i0 - 1, i0)],
+                     VOIGT[(1, 2)]: [(kk, jj, i0) for kk in (k0 - 1, k0) for jj in (j0 - 1, j0)]}
+            for a, idx in touch.items():
+                for t in idx:
+                    assert sv["sig"][a][t] == before[a][t], (a, t)
+                # a shear point that does not touch the cell is updated
+                far = (k0, j0 - 3, i0 - 3)
+                assert sv["sig"][a][far] != before[a][far]
+        states.append(v.copy())
+    a, b = states
+    assert np.max(np.abs(a - b)) <= 1e-12 * np.max(np.abs(a))
+
+
 def test_difference_transpose_is_negative_of_other_type():
     """Zero-extended D+^T = -D- (the skew structure behind the exact adjoint)."""
     from oracle.assembly import d1

@@ -132,7 +132,9 @@ el_status el_grid_check(const el_grid *grid, const double *rec_xyz, int32_t nrec
 /*
  * Device workspace bytes a plan of this grid and receiver count needs
  * (fields, material maps, C-PML boundary slabs, PML tables, receiver
- * tables, reduction scratch).  Host-only; *bytes is written on success.
+ * tables, reduction scratch; with relaxation mechanisms the strength map and
+ * room for a point list and its memory variables of up to three velocity
+ * points per cell).  Host-only; *bytes is written on success.
  */
 el_status el_plan_bytes(const el_grid *grid, int32_t nrec, size_t *bytes);
 
@@ -280,11 +282,11 @@ el_status el_plan_field(el_plan plan, int32_t id, void **ptr, size_t *count);
 el_status el_plan_layout(el_plan plan, int64_t *row_pitch, int64_t *plane_pitch, int64_t *origin);
 
 /*
- * Extent of the relaxation sub-update (el_relaxation): the stencil tiles it
- * visits, those holding a velocity point with beta > 0, their cells, and the
- * (cell, component) velocity points with beta > 0, which it updates.  All
- * zero for a plan without relaxation mechanisms.  Any pointer may be NULL.
- * Host-only.
+ * Extent of the relaxation sub-update (el_relaxation): the stencil tiles
+ * holding a velocity point with beta > 0, their cells, and the (cell,
+ * component) velocity points with beta > 0, the list it updates (built once
+ * by el_plan_create).  All zero for a plan without relaxation mechanisms.
+ * Any pointer may be NULL.  Host-only.
  */
 el_status el_plan_relaxation(el_plan plan, int64_t *tiles, int64_t *cells, int64_t *points);
 

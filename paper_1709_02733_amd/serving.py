@@ -19,8 +19,9 @@ step count and receiver set) arrive as a Poisson stream.  Ways to serve them:
   steadiest throughput gain over plain).
 * hybrid (run_grouped with an executor): small requests join the group, large
   ones (which fill the device alone) run on executor slots, and the two
-  overlap on the device; its gain depends on how the process's streams share
-  the hardware queues.
+  overlap on the device.  The executor keeps two graph replays in flight per
+  slot (el_exec_set_ahead), so the group's launches never wait behind a large
+  request's whole time loop in a shared hardware queue.
 
 All paths run the same per-cell arithmetic in the same order per request, so
 each result is bitwise the same alone and in the mix.  The report gives
